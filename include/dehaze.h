@@ -1,0 +1,185 @@
+/*
+ * dehaze.h - C ABI of the MI355X (gfx950) PDE dehazing library.
+ *
+ * The library computes, for a hazy RGB image I, the front end of Section II-D
+ * (dark channel, transmission t, adaptive weight lambda(t)) with the
+ * atmospheric light A, the reconstruction Phi(I, t, A) of Section II-A, and
+ * solves the main PDE
+ *
+ *     -div(D(grad u) grad u) + lambda(t) G(u) = Phi(I, t, A),
+ *     D(grad u) = (|grad u| + eps)^-1,  u = 0 outside the image,
+ *
+ * discretised as in Appendix A-2 (face coefficients from the forward normal
+ * difference and the central tangential difference at the lower-index cell;
+ * G a (2R+1)^2 Gaussian with taps normalised to sum 1, zero outside the
+ * image), by one of three fixed-point iterations (Appendix A-1 and the
+ * lagged-diffusivity reading of it).
+ *
+ * Conventions for every entry point:
+ *   - Image pointers are DEVICE pointers owned by the caller.  The library
+ *     never frees them and keeps no reference after the call returns.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream).
+ *     Outputs are valid once that stream has been synchronised, except where
+ *     an entry point says it synchronises itself.
+ *   - Planar ("CHW") float images hold 3 planes of H rows; row r of plane c
+ *     starts at element (c * H + r) * pitch.  Interleaved ("HWC") images hold
+ *     3 values per pixel; row r starts at element 3 * r * pitch.  pitch >= W
+ *     counts pixels.  Outputs written by the library (u, t, t_d, lambda, ...)
+ *     use pitch W (dense) unless stated otherwise.
+ *   - Scratch memory ("workspace") is passed in by the caller: `ws` must be
+ *     a device buffer of at least the size the matching *_workspace_size call
+ *     reports, aligned to 256 bytes.  Its contents need not be initialised.
+ *   - Return value: DEHAZE_OK (0) or a negative DEHAZE_E* code; no exception
+ *     crosses the ABI.  dehaze_last_error() gives a message for the calling
+ *     thread's last failure.
+ *   - Calls on different contexts may run concurrently from different host
+ *     threads; one context must not be used by two threads at once.
+ */
+#ifndef DEHAZE_H
+#define DEHAZE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ error codes */
+#define DEHAZE_OK          0
+#define DEHAZE_EINVAL     -1  /* bad size, parameter or NULL required pointer */
+#define DEHAZE_ENOMEM     -2  /* workspace too small */
+#define DEHAZE_EHIP       -3  /* a HIP runtime call failed (see dehaze_last_error) */
+#define DEHAZE_ENOTCONV   -4  /* rel_tol not reached within max_outer; u holds the last iterate */
+#define DEHAZE_ENONFINITE -5  /* NaN or Inf met in the input or the residual */
+
+/* ------------------------------------------------------------ enumerations */
+#define DEHAZE_U8  0          /* 8-bit codes; intensity = code / 255, correctly rounded */
+#define DEHAZE_F32 1          /* float32 intensities (not clipped) */
+
+#define DEHAZE_HWC 0          /* interleaved RGB */
+#define DEHAZE_CHW 1          /* planar RGB */
+
+#define DEHAZE_PAPER_EXPLICIT 0  /* u += tau r(u), Appendix A-1 as printed */
+#define DEHAZE_JACOBI         1  /* u += theta r(u) / diag(L_D(u)), D recomputed every sweep */
+#define DEHAZE_PICARD_KRYLOV  2  /* lagged diffusivity: u_{n+1} = L_{D(u_n)}^-1 Phi, each
+                                    linear solve by Jacobi-preconditioned BiCGSTAB */
+
+/* ------------------------------------------------------------ parameters */
+typedef struct dehaze_params {
+  int32_t patch;            /* dark-channel patch side, odd (Section II-D: 15) */
+  int32_t g_radius;         /* Gaussian radius R, kernel (2R+1)^2 (Appendix A-2: 2), 0..4 */
+  double  omega;            /* t = 1 - omega t_d (Section II-D: 0.95) */
+  double  t0;               /* Phi threshold (Section II-A: "small"; 0.1) */
+  double  eps;              /* D stabiliser (Section II-B: 1e-3) */
+  double  sigma;            /* Gaussian width (Section II-C: 2.0; default 1.5) */
+  double  lambda0;          /* lambda = lambda0 exp(-beta (1 - t)) (Section II-D: 0.5) */
+  double  beta_lambda;      /* (Section II-D: 3.0) */
+  double  tau;              /* explicit relaxation (Appendix A-1: 0.2) */
+  double  theta;            /* Jacobi damping (0.8) */
+  double  rel_tol;          /* stop when ||r||/||Phi|| <= rel_tol; <= 0: run exactly max_outer */
+  double  inner_rtol;       /* Krylov solve tolerance relative to its start residual */
+  int32_t scheme;           /* DEHAZE_PAPER_EXPLICIT, DEHAZE_JACOBI, DEHAZE_PICARD_KRYLOV */
+  int32_t max_outer;        /* sweeps (explicit, Jacobi) or lagged-diffusivity steps */
+  int32_t max_inner;        /* BiCGSTAB iterations per lagged-diffusivity step */
+  int32_t check_every;      /* residual test every this many outer steps (>= 1) */
+  int32_t atm_divisor;      /* A from the top max(1, HW / atm_divisor) dark-channel pixels */
+  int32_t warm_start;       /* 1: start from the network's prediction (needs loaded weights) */
+  int32_t nonlocal_term;    /* 0: drop lambda G (ablation) */
+  int32_t adaptive;         /* 0: lambda = lambda0 everywhere (ablation) */
+  int32_t edge_preserving;  /* 0: D = 1 (ablation; the solve becomes linear) */
+  int32_t sweeps_per_launch;/* sweeps fused per kernel launch (temporal blocking); 0 = library choice */
+  int32_t reserved[6];      /* must be zero */
+} dehaze_params;
+
+typedef struct dehaze_stats {
+  int32_t outer;            /* outer steps taken (sweeps or lagged-diffusivity steps) */
+  int32_t converged;        /* 1 if rel_tol was reached */
+  int64_t inner;            /* BiCGSTAB iterations in total */
+  int64_t applications;     /* operator applications (sweeps or matrix-vector products) */
+  double  rel_residual;     /* ||Phi - L_{D(u)} u|| / ||Phi|| at the returned u (float64 sum) */
+  double  rel_residual0;    /* the same at the starting iterate */
+  float   A[3];             /* atmospheric light used */
+  int32_t status;           /* DEHAZE_OK, DEHAZE_ENOTCONV or DEHAZE_ENONFINITE for this image */
+} dehaze_stats;
+
+typedef struct dehaze_ctx dehaze_ctx;
+
+/* Fills *p with the defaults listed above (scheme = DEHAZE_PICARD_KRYLOV,
+   max_outer = 5000, max_inner = 8, rel_tol = 1e-5, inner_rtol = 0.1,
+   check_every = 8).  Returns DEHAZE_EINVAL for NULL. */
+int dehaze_params_default(dehaze_params* p);
+
+/* sizeof(dehaze_params) and sizeof(dehaze_stats), so bindings can check their mirrors. */
+size_t dehaze_params_size(void);
+size_t dehaze_stats_size(void);
+
+/* Creates a context on HIP device `device` (it becomes current for the
+   calling thread).  The context owns kernel-launch tables, captured graphs
+   and the network weights.  DEHAZE_EHIP if the device cannot be used. */
+int dehaze_ctx_create(dehaze_ctx** ctx, int device);
+void dehaze_ctx_destroy(dehaze_ctx* ctx);
+
+/* Message for the calling thread's last failure ("" if none). */
+const char* dehaze_last_error(void);
+const char* dehaze_strerror(int code);
+
+/* ------------------------------------------------------------ front end
+ * Section II-D (dark channel, t = clamp(1 - omega t_d, 0, 1), lambda(t)) and
+ * Section II-A (Phi), with A from the dark-channel-prior rule (the paper
+ * takes A as given): the top max(1, HW / atm_divisor) pixels of the raw dark
+ * channel (ties to the lower linear index), then the one with the largest
+ * R+G+B summed in float64 as (R+G)+B (ties to the lower index).
+ *
+ *   I        image (dtype, layout, pitch as above), H, W >= 1
+ *   A_in     3 floats on the device, or NULL to estimate A
+ *   dark     raw dark channel min_c min_patch I^c (H x W float, nullable)
+ *   dark_u8  the same as 8-bit codes (H x W, nullable; only for DEHAZE_U8)
+ *   t_d      min_c min_patch I^c / A^c, float32 division (H x W, nullable)
+ *   t, lam   transmission and lambda(t) (H x W, nullable)
+ *   phi      Phi^c = (I^c - A^c (1 - t)) / max(t, t0) (planar, pitch W, nullable)
+ *   A_out    3 floats on the device receiving A (required)
+ * Errors: EINVAL (H or W < 1, pitch < W, even or non-positive patch,
+ * t0, eps or sigma <= 0, omega outside (0, 1], unknown dtype or layout, NULL
+ * I or A_out), ENOMEM (ws_bytes too small), EHIP.  A_in lives on the device
+ * and is not read back: a non-positive A_in gives non-finite t_d, t, lam and
+ * phi, which a later dehaze_solve reports as DEHAZE_ENONFINITE. */
+size_t dehaze_prior_workspace_size(int H, int W, const dehaze_params* p);
+int dehaze_prior(dehaze_ctx* ctx, const void* I, int dtype, int layout, int H, int W, int pitch,
+                 const dehaze_params* p, const float* A_in,
+                 float* dark, uint8_t* dark_u8, float* t_d, float* t, float* lam, float* phi,
+                 float* A_out, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------ one image solve
+ * Builds lambda(t) and Phi(I, t, A) from the given t (H x W, pitch W) and A
+ * (3 device floats), then iterates p->scheme from u0 (planar, pitch W;
+ * NULL = Phi, or the network when p->warm_start) into u (planar, pitch W).
+ *   DEHAZE_PAPER_EXPLICIT, DEHAZE_JACOBI: p->max_outer sweeps, each one pass
+ *     of the face-coefficient recompute and the update (Appendix A-1).
+ *   DEHAZE_PICARD_KRYLOV: lagged-diffusivity steps; the residual of the
+ *     current iterate is formed in float64 from a float32 hi/lo pair, each
+ *     correction L_{D(u_n)} delta = r_n is solved by BiCGSTAB in float32.
+ * With rel_tol > 0 the solve stops once rho <= rel_tol (tested every
+ * check_every outer steps) and returns DEHAZE_ENOTCONV if max_outer passes
+ * first.  `stats` (host, nullable) is filled; a non-NULL stats, or
+ * rel_tol > 0, makes the call synchronise `stream`.
+ * u is not clipped: the solution of the PDE exceeds the [0, 1] range. */
+size_t dehaze_solve_workspace_size(int H, int W, const dehaze_params* p);
+int dehaze_solve(dehaze_ctx* ctx, const void* I, int dtype, int layout, int H, int W, int pitch,
+                 const float* t, const float* A, const dehaze_params* p, const float* u0,
+                 float* u, void* ws, size_t ws_bytes, dehaze_stats* stats, void* stream);
+
+/* ------------------------------------------------------------ residual
+ * rho = ||Phi - L_{D(u)} u||_2 / ||Phi||_2 over all channels, for planar
+ * u, phi (pitch W) and lam (H x W): the quantity the main PDE sets to zero.
+ * r (planar, pitch W, nullable) receives Phi - L_{D(u)} u.  Synchronises
+ * `stream` and writes *rho (host). */
+size_t dehaze_residual_workspace_size(int H, int W, const dehaze_params* p);
+int dehaze_residual(dehaze_ctx* ctx, const float* u, const float* phi, const float* lam,
+                    int H, int W, const dehaze_params* p, float* r, double* rho,
+                    void* ws, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DEHAZE_H */

@@ -1,0 +1,232 @@
+"""Thin ctypes binding of libdehaze.so (include/dehaze.h).
+
+Only argument marshalling lives here: torch tensors provide device memory and
+the current HIP stream, every computation runs in the library's kernels.  If
+the library has not been built, importing this module raises ImportError:
+there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_double, c_float, c_int, c_int32, c_int64, c_size_t, c_uint8, c_void_p
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdehaze.so")
+
+OK, EINVAL, ENOMEM, EHIP, ENOTCONV, ENONFINITE = 0, -1, -2, -3, -4, -5
+U8, F32 = 0, 1
+HWC, CHW = 0, 1
+PAPER_EXPLICIT, JACOBI, PICARD_KRYLOV = 0, 1, 2
+SCHEMES = {"explicit": PAPER_EXPLICIT, "jacobi": JACOBI, "picard": PICARD_KRYLOV}
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("patch", c_int32), ("g_radius", c_int32),
+        ("omega", c_double), ("t0", c_double), ("eps", c_double), ("sigma", c_double),
+        ("lambda0", c_double), ("beta_lambda", c_double), ("tau", c_double), ("theta", c_double),
+        ("rel_tol", c_double), ("inner_rtol", c_double),
+        ("scheme", c_int32), ("max_outer", c_int32), ("max_inner", c_int32), ("check_every", c_int32),
+        ("atm_divisor", c_int32), ("warm_start", c_int32), ("nonlocal_term", c_int32),
+        ("adaptive", c_int32), ("edge_preserving", c_int32), ("sweeps_per_launch", c_int32),
+        ("reserved", c_int32 * 6),
+    ]
+
+    def replace(self, **kw) -> "Params":
+        p = Params()
+        ctypes.pointer(p)[0] = self
+        for k, v in kw.items():
+            if k == "scheme" and isinstance(v, str):
+                v = SCHEMES[v]
+            setattr(p, k, v)
+        return p
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("outer", c_int32), ("converged", c_int32), ("inner", c_int64), ("applications", c_int64),
+        ("rel_residual", c_double), ("rel_residual0", c_double), ("A", c_float * 3), ("status", c_int32),
+    ]
+
+    def as_dict(self) -> dict:
+        return {"outer": self.outer, "converged": bool(self.converged), "inner": self.inner,
+                "applications": self.applications, "rel_residual": self.rel_residual,
+                "rel_residual0": self.rel_residual0, "A": list(self.A), "status": self.status}
+
+
+class DehazeError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2506_08793_amd.build`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+_P = POINTER(Params)
+_S = POINTER(Stats)
+
+_SIGS = {
+    "dehaze_params_default": (c_int, [_P]),
+    "dehaze_params_size": (c_size_t, []),
+    "dehaze_stats_size": (c_size_t, []),
+    "dehaze_ctx_create": (c_int, [POINTER(c_void_p), c_int]),
+    "dehaze_ctx_destroy": (None, [c_void_p]),
+    "dehaze_last_error": (ctypes.c_char_p, []),
+    "dehaze_strerror": (ctypes.c_char_p, [c_int]),
+    "dehaze_prior_workspace_size": (c_size_t, [c_int, c_int, _P]),
+    "dehaze_prior": (c_int, [c_void_p, c_void_p, c_int, c_int, c_int, c_int, c_int, _P, c_void_p,
+                             c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                             c_void_p, c_size_t, c_void_p]),
+    "dehaze_solve_workspace_size": (c_size_t, [c_int, c_int, _P]),
+    "dehaze_solve": (c_int, [c_void_p, c_void_p, c_int, c_int, c_int, c_int, c_int, c_void_p, c_void_p, _P,
+                             c_void_p, c_void_p, c_void_p, c_size_t, _S, c_void_p]),
+    "dehaze_residual_workspace_size": (c_size_t, [c_int, c_int, _P]),
+    "dehaze_residual": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, _P, c_void_p,
+                                POINTER(c_double), c_void_p, c_size_t, c_void_p]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _fn = getattr(_lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+
+if _lib.dehaze_params_size() != ctypes.sizeof(Params) or _lib.dehaze_stats_size() != ctypes.sizeof(Stats):
+    raise ImportError("dehaze_params / dehaze_stats layout mismatch between binding and library")
+
+EXPORTED = tuple(_SIGS)
+
+
+def lib():
+    return _lib
+
+
+def _check(rc: int, allow=(OK,)) -> int:
+    if rc not in allow:
+        raise DehazeError(rc, _lib.dehaze_last_error().decode() or _lib.dehaze_strerror(rc).decode())
+    return rc
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def dehaze_params_default(**kw) -> Params:
+    p = Params()
+    _check(_lib.dehaze_params_default(ctypes.byref(p)))
+    return p.replace(**kw) if kw else p
+
+
+class Context:
+    """Owns a dehaze_ctx on one device."""
+
+    def __init__(self, device: int = 0):
+        h = c_void_p()
+        _check(_lib.dehaze_ctx_create(ctypes.byref(h), device))
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            _lib.dehaze_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _image_args(I: torch.Tensor, layout: str):
+    """(dtype, layout, H, W, pitch) of a device image; strides of size-1 dims are ignored."""
+    if not I.is_cuda:
+        raise ValueError("image must be a device tensor")
+    dtype = {torch.uint8: U8, torch.float32: F32}[I.dtype]
+    if layout == "CHW":
+        _, H, W = I.shape
+        pitch = I.stride(1) if H > 1 else W
+        if (W > 1 and I.stride(2) != 1) or I.stride(0) != H * pitch or pitch < W:
+            raise ValueError("CHW image must be row-contiguous with planes packed")
+        return dtype, CHW, H, W, pitch
+    H, W, _ = I.shape
+    pitch = I.stride(0) // 3 if H > 1 else W
+    if I.stride(2) != 1 or (W > 1 and I.stride(1) != 3) or (H > 1 and I.stride(0) % 3) or pitch < W:
+        raise ValueError("HWC image must be pixel-contiguous")
+    return dtype, HWC, H, W, pitch
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def dehaze_prior(ctx: Context, I: torch.Tensor, params: Params = None, A_in: torch.Tensor = None,
+                 layout: str = "CHW", outputs=("dark", "t_d", "t", "lam", "phi")) -> dict:
+    """Front end: returns the requested outputs plus A (3 floats) as device tensors."""
+    p = params or dehaze_params_default()
+    dtype, lay, H, W, pitch = _image_args(I, layout)
+    dev = I.device
+    out = {}
+    for name in outputs:
+        shape = (3, H, W) if name == "phi" else (H, W)
+        out[name] = torch.empty(shape, dtype=torch.uint8 if name == "dark_u8" else torch.float32, device=dev)
+    A = torch.empty(3, dtype=torch.float32, device=dev)
+    ws = _workspace(_lib.dehaze_prior_workspace_size(H, W, ctypes.byref(p)), dev)
+    _check(_lib.dehaze_prior(ctx.handle, I.data_ptr(), dtype, lay, H, W, pitch, ctypes.byref(p), _ptr(A_in),
+                             _ptr(out.get("dark")), _ptr(out.get("dark_u8")), _ptr(out.get("t_d")),
+                             _ptr(out.get("t")), _ptr(out.get("lam")), _ptr(out.get("phi")), A.data_ptr(),
+                             ws.data_ptr(), ws.numel(), _stream()))
+    out["A"] = A
+    out["_ws"] = ws  # keeps the workspace alive until the caller synchronises
+    return out
+
+
+def dehaze_solve(ctx: Context, I: torch.Tensor, t: torch.Tensor, A: torch.Tensor, params: Params = None,
+                 u0: torch.Tensor = None, u: torch.Tensor = None, layout: str = "CHW", stats: bool = True,
+                 ws: torch.Tensor = None):
+    """Solve the PDE for one image; returns (u, stats dict or None)."""
+    p = params or dehaze_params_default()
+    dtype, lay, H, W, pitch = _image_args(I, layout)
+    dev = I.device
+    for name, tens, shape in (("t", t, (H, W)), ("A", A, (3,)), ("u0", u0, (3, H, W))):
+        if tens is not None and (tuple(tens.shape) != shape or not tens.is_contiguous()
+                                 or tens.dtype != torch.float32 or not tens.is_cuda):
+            raise ValueError(f"{name} must be a contiguous float32 device tensor of shape {shape}")
+    if u is None:
+        u = torch.empty((3, H, W), dtype=torch.float32, device=dev)
+    need = _lib.dehaze_solve_workspace_size(H, W, ctypes.byref(p))
+    if ws is None or ws.numel() < need:
+        ws = _workspace(need, dev)
+    st = Stats() if stats else None
+    rc = _lib.dehaze_solve(ctx.handle, I.data_ptr(), dtype, lay, H, W, pitch, t.data_ptr(), A.data_ptr(),
+                           ctypes.byref(p), _ptr(u0), u.data_ptr(), ws.data_ptr(), ws.numel(),
+                           ctypes.byref(st) if st is not None else None, _stream())
+    _check(rc, allow=(OK, ENOTCONV))
+    return u, (st.as_dict() if st is not None else None)
+
+
+def solve_workspace(H: int, W: int, params: Params, device="cuda") -> torch.Tensor:
+    return _workspace(_lib.dehaze_solve_workspace_size(H, W, ctypes.byref(params)), device)
+
+
+def dehaze_residual(ctx: Context, u: torch.Tensor, phi: torch.Tensor, lam: torch.Tensor, params: Params = None,
+                    want_r: bool = False):
+    """rho = ||Phi - L_{D(u)} u|| / ||Phi||; returns (rho, r or None)."""
+    p = params or dehaze_params_default()
+    _, H, W = u.shape
+    for tens in (u, phi, lam):
+        if not (tens.is_cuda and tens.is_contiguous() and tens.dtype == torch.float32):
+            raise ValueError("u, phi, lam must be contiguous float32 device tensors")
+    r = torch.empty_like(u) if want_r else None
+    ws = _workspace(_lib.dehaze_residual_workspace_size(H, W, ctypes.byref(p)), u.device)
+    rho = c_double()
+    _check(_lib.dehaze_residual(ctx.handle, u.data_ptr(), phi.data_ptr(), lam.data_ptr(), H, W, ctypes.byref(p),
+                                _ptr(r), ctypes.byref(rho), ws.data_ptr(), ws.numel(), _stream()))
+    return rho.value, r

@@ -1,0 +1,260 @@
+// C ABI entry points: argument checks, workspace carving and the order of
+// kernel launches.  All arithmetic happens in the kernels of the other
+// translation units.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "internal.hpp"
+#include "solver.hpp"
+
+namespace dz {
+
+namespace {
+thread_local char g_err[512] = "";
+}
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+void clear_error() { g_err[0] = '\0'; }
+
+int check_params(const dehaze_params* p) {
+  if (!p) { set_error("params is NULL"); return DEHAZE_EINVAL; }
+  if (p->patch < 1 || p->patch % 2 == 0 || p->patch > kMaxPatch) {
+    set_error("patch %d must be odd and in 1..%d", p->patch, kMaxPatch);
+    return DEHAZE_EINVAL;
+  }
+  if (p->g_radius < 0 || p->g_radius > 4) { set_error("g_radius %d outside 0..4", p->g_radius); return DEHAZE_EINVAL; }
+  if (!(p->t0 > 0.0) || !(p->eps > 0.0) || !(p->sigma > 0.0)) {
+    set_error("t0, eps and sigma must be positive"); return DEHAZE_EINVAL;
+  }
+  if (!(p->omega > 0.0 && p->omega <= 1.0)) { set_error("omega must lie in (0, 1]"); return DEHAZE_EINVAL; }
+  if (!(p->lambda0 >= 0.0) || !std::isfinite(p->beta_lambda)) {
+    set_error("lambda0 must be >= 0 and beta finite"); return DEHAZE_EINVAL;
+  }
+  if (p->atm_divisor < 1) { set_error("atm_divisor must be >= 1"); return DEHAZE_EINVAL; }
+  if (p->scheme < DEHAZE_PAPER_EXPLICIT || p->scheme > DEHAZE_PICARD_KRYLOV) {
+    set_error("unknown scheme %d", p->scheme); return DEHAZE_EINVAL;
+  }
+  if (p->max_outer < 0 || p->max_inner < 1 || p->check_every < 1) {
+    set_error("max_outer >= 0, max_inner >= 1 and check_every >= 1 required"); return DEHAZE_EINVAL;
+  }
+  if (!(p->theta > 0.0) || !std::isfinite(p->tau)) { set_error("theta must be positive"); return DEHAZE_EINVAL; }
+  if (p->sweeps_per_launch < 0) { set_error("sweeps_per_launch must be >= 0"); return DEHAZE_EINVAL; }
+  return DEHAZE_OK;
+}
+
+int check_image(const void* I, int dtype, int layout, int H, int W, int pitch) {
+  if (!I) { set_error("image pointer is NULL"); return DEHAZE_EINVAL; }
+  if (H < 1 || W < 1) { set_error("image must be at least 1 x 1 (got %d x %d)", H, W); return DEHAZE_EINVAL; }
+  if (static_cast<long long>(H) * W > (1LL << 30)) { set_error("image too large"); return DEHAZE_EINVAL; }
+  if (pitch < W) { set_error("pitch %d < width %d", pitch, W); return DEHAZE_EINVAL; }
+  if (dtype != DEHAZE_U8 && dtype != DEHAZE_F32) { set_error("unknown dtype %d", dtype); return DEHAZE_EINVAL; }
+  if (layout != DEHAZE_HWC && layout != DEHAZE_CHW) { set_error("unknown layout %d", layout); return DEHAZE_EINVAL; }
+  return DEHAZE_OK;
+}
+
+// ------------------------------------------------------------ workspace plans
+struct PriorPlan {
+  PriorBufs b{};
+  size_t bytes = 0;
+};
+
+static PriorPlan plan_prior(void* ws, int H, int W) {
+  PriorPlan pl;
+  const int P = padded_pitch(W);
+  const size_t plane = static_cast<size_t>(H) * P;
+  Carver cv(ws, ~size_t(0));
+  pl.b.P = P;
+  pl.b.Ip = cv.take<float>(3 * plane);
+  pl.b.mrow = cv.take<float>(3 * plane);
+  pl.b.m = cv.take<float>(3 * plane);
+  pl.b.dc = cv.take<float>(plane);
+  pl.b.sel = cv.take<char>(prior_scratch_bytes(H, W));
+  pl.bytes = cv.used();
+  return pl;
+}
+
+}  // namespace dz
+
+using namespace dz;
+
+struct dehaze_ctx {
+  Ctx c;
+};
+
+extern "C" {
+
+int dehaze_params_default(dehaze_params* p) {
+  if (!p) { set_error("params is NULL"); return DEHAZE_EINVAL; }
+  std::memset(p, 0, sizeof(*p));
+  p->patch = 15;
+  p->g_radius = 2;
+  p->omega = 0.95;
+  p->t0 = 0.1;
+  p->eps = 1e-3;
+  p->sigma = 1.5;
+  p->lambda0 = 0.5;
+  p->beta_lambda = 3.0;
+  p->tau = 0.2;
+  p->theta = 0.8;
+  p->rel_tol = 1e-5;
+  p->inner_rtol = 0.1;
+  p->scheme = DEHAZE_PICARD_KRYLOV;
+  p->max_outer = 5000;
+  p->max_inner = 8;
+  p->check_every = 8;
+  p->atm_divisor = 1000;
+  p->warm_start = 0;
+  p->nonlocal_term = 1;
+  p->adaptive = 1;
+  p->edge_preserving = 1;
+  p->sweeps_per_launch = 0;
+  return DEHAZE_OK;
+}
+
+size_t dehaze_params_size(void) { return sizeof(dehaze_params); }
+size_t dehaze_stats_size(void) { return sizeof(dehaze_stats); }
+
+const char* dehaze_last_error(void) { return dz::g_err; }
+
+const char* dehaze_strerror(int code) {
+  switch (code) {
+    case DEHAZE_OK: return "ok";
+    case DEHAZE_EINVAL: return "invalid argument";
+    case DEHAZE_ENOMEM: return "workspace too small";
+    case DEHAZE_EHIP: return "HIP runtime error";
+    case DEHAZE_ENOTCONV: return "tolerance not reached";
+    case DEHAZE_ENONFINITE: return "non-finite value";
+    default: return "unknown error";
+  }
+}
+
+int dehaze_ctx_create(dehaze_ctx** out, int device) {
+  clear_error();
+  if (!out) { set_error("ctx pointer is NULL"); return DEHAZE_EINVAL; }
+  *out = nullptr;
+  DZ_HIP(hipSetDevice(device));
+  hipDeviceProp_t prop;
+  DZ_HIP(hipGetDeviceProperties(&prop, device));
+  dehaze_ctx* ctx = new (std::nothrow) dehaze_ctx();
+  if (!ctx) { set_error("out of host memory"); return DEHAZE_EINVAL; }
+  ctx->c.device = device;
+  ctx->c.num_cus = prop.multiProcessorCount;
+  ctx->c.lds_bytes = static_cast<int>(prop.sharedMemPerBlock);
+  *out = ctx;
+  return DEHAZE_OK;
+}
+
+void dehaze_ctx_destroy(dehaze_ctx* ctx) {
+  if (!ctx) return;
+  solver_release(ctx->c);
+  delete ctx;
+}
+
+size_t dehaze_prior_workspace_size(int H, int W, const dehaze_params* p) {
+  (void)p;
+  if (H < 1 || W < 1) return 0;
+  return plan_prior(nullptr, H, W).bytes;
+}
+
+int dehaze_prior(dehaze_ctx* ctx, const void* I, int dtype, int layout, int H, int W, int pitch,
+                 const dehaze_params* p, const float* A_in, float* dark, uint8_t* dark_u8, float* t_d,
+                 float* t, float* lam, float* phi, float* A_out, void* ws, size_t ws_bytes, void* stream) {
+  clear_error();
+  if (!ctx) { set_error("ctx is NULL"); return DEHAZE_EINVAL; }
+  int rc = check_image(I, dtype, layout, H, W, pitch);
+  if (rc) return rc;
+  if ((rc = check_params(p))) return rc;
+  if (!A_out) { set_error("A_out is NULL"); return DEHAZE_EINVAL; }
+  if (dark_u8 && dtype != DEHAZE_U8) { set_error("dark_u8 needs 8-bit input"); return DEHAZE_EINVAL; }
+  PriorPlan pl = plan_prior(ws, H, W);
+  if (!ws || ws_bytes < pl.bytes) {
+    set_error("prior workspace needs %zu bytes, got %zu", pl.bytes, ws_bytes);
+    return DEHAZE_ENOMEM;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  DZ_HIP(hipSetDevice(ctx->c.device));
+  if ((rc = launch_patch_min(I, dtype, layout, H, W, pitch, p->patch, pl.b, dark, dark_u8, s))) return rc;
+  const float* A = A_out;
+  if (A_in) {
+    if (A_in != A_out) DZ_HIP(hipMemcpyAsync(A_out, A_in, 3 * sizeof(float), hipMemcpyDeviceToDevice, s));
+  } else {
+    if ((rc = launch_airlight(pl.b, H, W, p->atm_divisor, A_out, s))) return rc;
+  }
+  FusedOut o{t_d, t, lam, phi, W};
+  return launch_prior_fused(pl.b.m, pl.b.Ip, pl.b.P, nullptr, 0, A, H, W, *p, o, s);
+}
+
+size_t dehaze_solve_workspace_size(int H, int W, const dehaze_params* p) {
+  if (H < 1 || W < 1 || !p) return 0;
+  return solver_workspace_bytes(H, W, *p);
+}
+
+int dehaze_solve(dehaze_ctx* ctx, const void* I, int dtype, int layout, int H, int W, int pitch, const float* t,
+                 const float* A, const dehaze_params* p, const float* u0, float* u, void* ws, size_t ws_bytes,
+                 dehaze_stats* stats, void* stream) {
+  clear_error();
+  if (!ctx) { set_error("ctx is NULL"); return DEHAZE_EINVAL; }
+  int rc = check_image(I, dtype, layout, H, W, pitch);
+  if (rc) return rc;
+  if ((rc = check_params(p))) return rc;
+  if (!t || !A || !u) { set_error("t, A and u are required"); return DEHAZE_EINVAL; }
+  const size_t need = solver_workspace_bytes(H, W, *p);
+  if (!ws || ws_bytes < need) {
+    set_error("solve workspace needs %zu bytes, got %zu", need, ws_bytes);
+    return DEHAZE_ENOMEM;
+  }
+  DZ_HIP(hipSetDevice(ctx->c.device));
+  SolveArgs a{I, dtype, layout, H, W, pitch, t, A, u0, u, ws, ws_bytes};
+  return solve_one(ctx->c, a, *p, stats, static_cast<hipStream_t>(stream));
+}
+
+size_t dehaze_residual_workspace_size(int H, int W, const dehaze_params* p) {
+  (void)p;
+  if (H < 1 || W < 1) return 0;
+  Carver cv(nullptr, ~size_t(0));
+  cv.take<double>(2 * static_cast<size_t>(sweep_num_blocks(H, W)));
+  cv.take<double>(2);
+  return cv.used();
+}
+
+int dehaze_residual(dehaze_ctx* ctx, const float* u, const float* phi, const float* lam, int H, int W,
+                    const dehaze_params* p, float* r, double* rho, void* ws, size_t ws_bytes, void* stream) {
+  clear_error();
+  if (!ctx) { set_error("ctx is NULL"); return DEHAZE_EINVAL; }
+  if (!u || !phi || !lam || !rho) { set_error("u, phi, lam and rho are required"); return DEHAZE_EINVAL; }
+  if (H < 1 || W < 1) { set_error("image must be at least 1 x 1"); return DEHAZE_EINVAL; }
+  int rc = check_params(p);
+  if (rc) return rc;
+  const size_t need = dehaze_residual_workspace_size(H, W, p);
+  if (!ws || ws_bytes < need) {
+    set_error("residual workspace needs %zu bytes, got %zu", need, ws_bytes);
+    return DEHAZE_ENOMEM;
+  }
+  DZ_HIP(hipSetDevice(ctx->c.device));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Carver cv(ws, ws_bytes);
+  const int nb = sweep_num_blocks(H, W);
+  double* part = cv.take<double>(2 * static_cast<size_t>(nb));
+  double* sums = cv.take<double>(2);
+  const OpConst oc = make_opconst(*p);
+  if ((rc = launch_sweep(kResidual, u, r, phi, lam, H, W, W, oc, part, s))) return rc;
+  if ((rc = launch_reduce_pairs(part, nb, sums, s))) return rc;
+  double h[2];
+  DZ_HIP(hipMemcpyAsync(h, sums, sizeof(h), hipMemcpyDeviceToHost, s));
+  DZ_HIP(hipStreamSynchronize(s));
+  *rho = h[1] > 0.0 ? std::sqrt(h[0]) / std::sqrt(h[1]) : std::sqrt(h[0]);
+  if (!std::isfinite(*rho)) { set_error("residual is not finite"); return DEHAZE_ENONFINITE; }
+  return DEHAZE_OK;
+}
+
+}  // extern "C"

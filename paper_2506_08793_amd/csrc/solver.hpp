@@ -1,0 +1,23 @@
+// One-image solve orchestration (front-end reuse, scheme dispatch, stopping).
+#pragma once
+
+#include "internal.hpp"
+
+namespace dz {
+
+struct SolveArgs {
+  const void* I;
+  int dtype, layout, H, W, pitch;
+  const float* t;   // H x W, pitch W
+  const float* A;   // 3 device floats
+  const float* u0;  // planar, pitch W, nullable
+  float* u;         // planar, pitch W
+  void* ws;
+  size_t ws_bytes;
+};
+
+size_t solver_workspace_bytes(int H, int W, const dehaze_params& p);
+int solve_one(Ctx& ctx, const SolveArgs& a, const dehaze_params& p, dehaze_stats* stats, hipStream_t s);
+void solver_release(Ctx& ctx);
+
+}  // namespace dz
