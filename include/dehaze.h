@@ -89,7 +89,9 @@ typedef struct dehaze_params {
   int32_t adaptive;         /* 0: lambda = lambda0 everywhere (ablation) */
   int32_t edge_preserving;  /* 0: D = 1 (ablation; the solve becomes linear) */
   int32_t sweeps_per_launch;/* sweeps fused per kernel launch (temporal blocking); 0 = library choice */
-  int32_t reserved[6];      /* must be zero */
+  int32_t inner_refine;     /* extra defect-correction passes per lagged-diffusivity step: with D frozen
+                               at u_n, re-form Phi - L_{D(u_n)} u in float64 and solve again (0 = one solve) */
+  int32_t reserved[5];      /* must be zero */
 } dehaze_params;
 
 typedef struct dehaze_stats {

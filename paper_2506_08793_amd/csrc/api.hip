@@ -49,6 +49,8 @@ int check_params(const dehaze_params* p) {
   }
   if (!(p->theta > 0.0) || !std::isfinite(p->tau)) { set_error("theta must be positive"); return DEHAZE_EINVAL; }
   if (p->sweeps_per_launch < 0) { set_error("sweeps_per_launch must be >= 0"); return DEHAZE_EINVAL; }
+  if (p->inner_refine < 0) { set_error("inner_refine must be >= 0"); return DEHAZE_EINVAL; }
+  if (!(p->inner_rtol > 0.0)) { set_error("inner_rtol must be positive"); return DEHAZE_EINVAL; }
   return DEHAZE_OK;
 }
 

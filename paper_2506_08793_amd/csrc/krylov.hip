@@ -1,0 +1,676 @@
+// Kernels of the lagged-diffusivity solve (see krylov.hpp for the scheme).
+//
+// All kernels walk the tiles of every image in the batch (one 64 x 16 tile
+// per workgroup).  Per-image sums (norms, BiCGSTAB inner products) are formed
+// deterministically: each tile writes its partial sums, and the last tile of
+// the image to finish (an atomic counter) adds the partials in a fixed order
+// and updates the image's scalars for the next launch.
+#include <cmath>
+
+#include "krylov.hpp"
+
+namespace dz {
+
+KConst make_kconst(const dehaze_params& p) {
+  KConst c{};
+  const int R = p.g_radius;
+  double g[9], s = 0.0;
+  for (int a = -R; a <= R; ++a) {
+    g[a + R] = std::exp(-(a * a) / (2.0 * p.sigma * p.sigma));
+    s += g[a + R];
+  }
+  for (int a = 0; a < 2 * R + 1; ++a) {
+    c.w64[a] = g[a] / s;
+    c.w[a] = static_cast<float>(c.w64[a]);
+  }
+  c.wc2_64 = c.w64[R] * c.w64[R];
+  c.wc2 = static_cast<float>(c.wc2_64);
+  c.eps = static_cast<float>(p.eps);
+  c.eps64 = p.eps;
+  c.rel_tol = p.rel_tol;
+  c.eta = p.inner_rtol;
+  c.R = R;
+  c.nonlocal_term = p.nonlocal_term;
+  c.edge_preserving = p.edge_preserving;
+  return c;
+}
+
+int krylov_tiles(int H, int W) { return ((W + kKTX - 1) / kKTX) * ((H + kKTY - 1) / kKTY); }
+
+namespace {
+
+struct KCarve {
+  KImg img;
+  size_t bytes;
+};
+
+KCarve carve(void* base, int H, int W, int tile0) {
+  KCarve k{};
+  const int P = padded_pitch(W + 1);
+  const size_t plane = static_cast<size_t>(H) * P;
+  const size_t plane_y = static_cast<size_t>(H + 1) * P;
+  Carver cv(base, ~size_t(0));
+  KImg& m = k.img;
+  m.H = H;
+  m.W = W;
+  m.P = P;
+  m.tiles_x = (W + kKTX - 1) / kKTX;
+  m.ntiles = krylov_tiles(H, W);
+  m.tile0 = tile0;
+  m.phi = cv.take<float>(3 * plane);
+  m.lam = cv.take<float>(plane);
+  m.u = cv.take<double>(3 * plane);
+  m.un = cv.take<double>(3 * plane);
+  m.Dx = cv.take<float>(3 * plane);
+  m.Dy = cv.take<float>(3 * plane_y);
+  m.invd = cv.take<float>(3 * plane);
+  m.rhat = cv.take<float>(3 * plane);
+  m.r = cv.take<float>(3 * plane);
+  m.p[0] = cv.take<float>(3 * plane);
+  m.p[1] = cv.take<float>(3 * plane);
+  m.v[0] = cv.take<float>(3 * plane);
+  m.v[1] = cv.take<float>(3 * plane);
+  m.s = cv.take<float>(3 * plane);
+  m.t = cv.take<float>(3 * plane);
+  m.x = cv.take<float>(3 * plane);
+  k.bytes = cv.used();
+  return k;
+}
+
+constexpr int NT = 256;
+constexpr int kPixPerThread = kKTX * kKTY / NT;  // 4
+
+struct TilePos {
+  int im, local, x0, y0;
+};
+
+__device__ __forceinline__ TilePos tile_pos(const KImg& I, int im, int g) {
+  TilePos t;
+  t.im = im;
+  t.local = g - I.tile0;
+  t.x0 = (t.local % I.tiles_x) * kKTX;
+  t.y0 = (t.local / I.tiles_x) * kKTY;
+  return t;
+}
+
+// Block sum of N doubles; the result is valid in thread 0.
+template <int N>
+__device__ __forceinline__ void block_sum(double (&v)[N]) {
+  __shared__ double red[N][NT / 64];
+  for (int k = 0; k < N; ++k)
+    for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_down(v[k], off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0)
+    for (int k = 0; k < N; ++k) red[k][wave] = v[k];
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int k = 0; k < N; ++k) {
+      double s = 0.0;
+      for (int w = 0; w < NT / 64; ++w) s += red[k][w];
+      v[k] = s;
+    }
+}
+
+// Writes this tile's N partial sums; returns true (in every thread) in the
+// last tile of the image to finish, with the image totals in tot[] (valid in
+// thread 0).  The totals are summed over tiles in index order.
+template <int N>
+__device__ bool finish_tile(double (&v)[N], double* part, int gtile, const KImg& I, KScal* sc,
+                            double (&tot)[N]) {
+  __shared__ int is_last;
+  block_sum<N>(v);
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < N; ++k) part[static_cast<size_t>(gtile) * kKPart + k] = v[k];
+    __threadfence();
+    const unsigned prev = atomicAdd(&sc->counter, 1u);
+    is_last = prev == static_cast<unsigned>(I.ntiles - 1);
+  }
+  __syncthreads();
+  if (!is_last) return false;
+  __threadfence();
+  for (int k = 0; k < N; ++k) tot[k] = 0.0;
+  // fixed assignment of tiles to threads and a fixed reduction tree
+  for (int q = threadIdx.x; q < I.ntiles; q += NT)
+    for (int k = 0; k < N; ++k) tot[k] += part[static_cast<size_t>(I.tile0 + q) * kKPart + k];
+  block_sum<N>(tot);
+  return true;
+}
+
+// ------------------------------------------------------------ init / output
+__global__ __launch_bounds__(NT) void k_scal_reset(KScal* scal, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  KScal z{};
+  z.converged = 0;
+  scal[i] = z;
+}
+
+__global__ __launch_bounds__(NT) void k_tile_map(int* tile_img, int tile0, int ntiles, int im) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ntiles) tile_img[tile0 + i] = im;
+}
+
+__global__ __launch_bounds__(NT) void k_set_desc(KImg* d, int i, KImg h) { d[i] = h; }
+
+__global__ __launch_bounds__(NT) void k_init_u(KImg I, const float* __restrict__ u0) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x >= I.W) return;
+  const size_t plane = static_cast<size_t>(I.H) * I.P;
+  for (int c = 0; c < 3; ++c) {
+    const size_t e = c * plane + static_cast<size_t>(y) * I.P + x;
+    const float v = u0 ? u0[(static_cast<size_t>(c) * I.H + y) * I.W + x] : I.phi[e];
+    I.u[e] = static_cast<double>(v);
+  }
+}
+
+__global__ __launch_bounds__(NT) void k_out_u(KImg I, float* __restrict__ out) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x >= I.W) return;
+  const size_t plane = static_cast<size_t>(I.H) * I.P;
+  for (int c = 0; c < 3; ++c)
+    out[(static_cast<size_t>(c) * I.H + y) * I.W + x] =
+        static_cast<float>(I.u[c * plane + static_cast<size_t>(y) * I.P + x]);
+}
+
+// ------------------------------------------------------------ residual pass
+// LINEAR = 0: r_n = Phi - L_{D(u_n)} u_n in float64 at the iterate u; stores D
+// per face (float32), the inverse Jacobi diagonal and r_n (float32) as the
+// inner right-hand side, and tests rho_n against rel_tol.
+// LINEAR = 1: Phi - L_{D(u_n)} u with D recomputed (float64, bit-identical to
+// the first pass) from the snapshot u_n and the operator applied to the
+// current u: the right-hand side of a defect-correction pass.
+template <int R, int LINEAR>
+__global__ __launch_bounds__(NT) void k_res(const KImg* __restrict__ imgs, KScal* scal,
+                                             const int* __restrict__ tile_img, double* part, KConst kc,
+                                             int final) {
+  constexpr int HALO = R > 1 ? R : 1;
+  constexpr int SX = kKTX + 2 * HALO, SY = kKTY + 2 * HALO;
+  __shared__ double us[SY][SX];                       // field the operator is applied to
+  __shared__ double ud[LINEAR ? SY : 1][LINEAR ? SX : 1];  // field D is taken from (LINEAR)
+  __shared__ double gh[kKTY + 2 * R][kKTX];
+  __shared__ double qx[kKTY][kKTX + 1];
+  __shared__ float dx[kKTY][kKTX + 1];
+  __shared__ double qy[kKTY + 1][kKTX];
+  __shared__ float dy[kKTY + 1][kKTX];
+  const int g = blockIdx.x;
+  const int im = tile_img[g];
+  const KImg I = imgs[im];
+  KScal* sc = scal + im;
+  if (!final && sc->converged) return;
+  const TilePos tp = tile_pos(I, im, g);
+  const int tid = threadIdx.x, tx = tid & (kKTX - 1), ty = tid / kKTX;
+  const int gx = tp.x0 + tx;
+  const size_t plane = static_cast<size_t>(I.H) * I.P;
+  const size_t plane_y = static_cast<size_t>(I.H + 1) * I.P;
+  double lv[kPixPerThread];
+  for (int k = 0; k < kPixPerThread; ++k) {
+    const int gy = tp.y0 + ty + 4 * k;
+    lv[k] = (kc.nonlocal_term && gx < I.W && gy < I.H) ? static_cast<double>(I.lam[static_cast<size_t>(gy) * I.P + gx])
+                                                      : 0.0;
+  }
+  double acc[3] = {0.0, 0.0, 0.0};  // ||r||^2 (float64), ||Phi||^2, ||r||^2 of the float32 copy
+  for (int c = 0; c < 3; ++c) {
+    const double* uc = I.u + c * plane;
+    const double* unc = I.un + c * plane;
+    for (int i = tid; i < SY * SX; i += NT) {
+      const int ly = i / SX, lx = i - (i / SX) * SX;
+      const int yy = tp.y0 - HALO + ly, xx = tp.x0 - HALO + lx;
+      const bool in = yy >= 0 && yy < I.H && xx >= 0 && xx < I.W;
+      const size_t e = static_cast<size_t>(yy) * I.P + xx;
+      us[ly][lx] = in ? uc[e] : 0.0;
+      if (LINEAR) ud[ly][lx] = in ? unc[e] : 0.0;
+    }
+    __syncthreads();
+    auto UD = [&](int y, int x) -> double { return LINEAR ? ud[y][x] : us[y][x]; };
+    if (kc.nonlocal_term) {
+      for (int i = tid; i < (kKTY + 2 * R) * kKTX; i += NT) {
+        const int j = i / kKTX, lx = i - (i / kKTX) * kKTX;
+        double s = 0.0;
+        for (int a = 0; a < 2 * R + 1; ++a) s += kc.w64[a] * us[HALO - R + j][HALO + lx - R + a];
+        gh[j][lx] = s;
+      }
+    }
+    for (int i = tid; i < kKTY * (kKTX + 1); i += NT) {
+      const int ly = i / (kKTX + 1), f = i - (i / (kKTX + 1)) * (kKTX + 1);
+      const int cy = HALO + ly, cx = HALO + f - 1;
+      const double gnd = UD(cy, cx + 1) - UD(cy, cx);
+      const double gtd = 0.5 * (UD(cy + 1, cx) - UD(cy - 1, cx));
+      const double D = kc.edge_preserving ? 1.0 / (sqrt(gnd * gnd + gtd * gtd) + kc.eps64) : 1.0;
+      qx[ly][f] = D * (us[cy][cx + 1] - us[cy][cx]);
+      dx[ly][f] = static_cast<float>(D);
+      const int y = tp.y0 + ly, gf = tp.x0 + f;
+      if (!LINEAR && y < I.H && ((f < kKTX && gf <= I.W) || (f == kKTX && gf == I.W)))
+        I.Dx[c * plane + static_cast<size_t>(y) * I.P + gf] = static_cast<float>(D);
+    }
+    for (int i = tid; i < (kKTY + 1) * kKTX; i += NT) {
+      const int f = i / kKTX, lx = i - (i / kKTX) * kKTX;
+      const int cy = HALO + f - 1, cx = HALO + lx;
+      const double gnd = UD(cy + 1, cx) - UD(cy, cx);
+      const double gtd = 0.5 * (UD(cy, cx + 1) - UD(cy, cx - 1));
+      const double D = kc.edge_preserving ? 1.0 / (sqrt(gnd * gnd + gtd * gtd) + kc.eps64) : 1.0;
+      qy[f][lx] = D * (us[cy + 1][cx] - us[cy][cx]);
+      dy[f][lx] = static_cast<float>(D);
+      const int x = tp.x0 + lx, gf = tp.y0 + f;
+      if (!LINEAR && x < I.W && ((f < kKTY && gf <= I.H) || (f == kKTY && gf == I.H)))
+        I.Dy[c * plane_y + static_cast<size_t>(gf) * I.P + x] = static_cast<float>(D);
+    }
+    __syncthreads();
+    for (int k = 0; k < kPixPerThread; ++k) {
+      const int ly = ty + 4 * k, gy = tp.y0 + ly;
+      if (gx < I.W && gy < I.H) {
+        const double div = (qx[ly][tx + 1] - qx[ly][tx]) + (qy[ly + 1][tx] - qy[ly][tx]);
+        double G = 0.0;
+        if (kc.nonlocal_term)
+          for (int b = 0; b < 2 * R + 1; ++b) G += kc.w64[b] * gh[ly + b][tx];
+        const size_t e = c * plane + static_cast<size_t>(gy) * I.P + gx;
+        const double ph = I.phi[e];
+        const double r = ph - (lv[k] * G - div);
+        const float b32 = static_cast<float>(r);
+        I.rhat[e] = b32;
+        if (!LINEAR) {
+          const float d = (dx[ly][tx] + dx[ly][tx + 1]) + (dy[ly][tx] + dy[ly + 1][tx]) +
+                          static_cast<float>(lv[k]) * kc.wc2;
+          I.invd[e] = 1.0f / d;
+        }
+        acc[0] += r * r;
+        acc[1] += ph * ph;
+        acc[2] += static_cast<double>(b32) * b32;
+      }
+    }
+    __syncthreads();
+  }
+  double tot[3];
+  if (!finish_tile<3>(acc, part, g, I, sc, tot)) return;
+  if (threadIdx.x != 0) return;
+  if (!LINEAR) {
+    if (sc->inner_this > 0) {  // account for the update applied since the last pass
+      sc->outer += 1;
+      sc->inner_total += sc->inner_this;
+      sc->inner_this = 0;
+    }
+    sc->res_evals += 1;
+    const double rel = tot[1] > 0.0 ? sqrt(tot[0] / tot[1]) : sqrt(tot[0]);
+    if (sc->res_evals == 1) sc->rel0 = rel;
+    sc->rel = rel;
+    if (!isfinite(rel)) {
+      sc->nonfinite = 1;
+      sc->converged = 1;
+    } else if (kc.rel_tol > 0.0 && rel <= kc.rel_tol) {
+      sc->converged = 1;
+    }
+  } else {
+    sc->res_evals += 1;
+  }
+  if (!final) {
+    sc->bnorm2 = tot[2];
+    sc->rho = tot[2];
+    sc->alpha = 1.0;
+    sc->omega = 1.0;
+    sc->beta = 0.0;
+    sc->half_done = 0;
+    sc->pass_inner = 0;
+    sc->inner_done = (tot[2] > 0.0 && isfinite(tot[2])) ? 0 : 1;
+  }
+  sc->counter = 0;
+}
+
+__global__ __launch_bounds__(NT) void k_snapshot(const KImg* __restrict__ imgs, const KScal* __restrict__ scal,
+                                                  const int* __restrict__ tile_img) {
+  const int g = blockIdx.x;
+  const int im = tile_img[g];
+  const KImg I = imgs[im];
+  if (scal[im].converged) return;
+  const TilePos tp = tile_pos(I, im, g);
+  const int tid = threadIdx.x, tx = tid & (kKTX - 1), ty = tid / kKTX;
+  const int gx = tp.x0 + tx;
+  const size_t plane = static_cast<size_t>(I.H) * I.P;
+  for (int c = 0; c < 3; ++c)
+    for (int k = 0; k < kPixPerThread; ++k) {
+      const int gy = tp.y0 + ty + 4 * k;
+      if (gx < I.W && gy < I.H) {
+        const size_t e = c * plane + static_cast<size_t>(gy) * I.P + gx;
+        I.un[e] = I.u[e];
+      }
+    }
+}
+
+// ------------------------------------------------------------ operator tile
+// Applies L_D (frozen D) to the field f staged in LDS (tile + halo) at the
+// tile's interior pixel (tx, ly); f is zero outside the image.
+template <int R, int HALO>
+__device__ __forceinline__ float apply_L(const float (&fs)[kKTY + 2 * HALO][kKTX + 2 * HALO],
+                                         const float (&gh)[kKTY + 2 * R][kKTX], const KImg& I, const KConst& kc,
+                                         int c, int gx, int gy, int tx, int ly, float lam) {
+  const size_t plane = static_cast<size_t>(I.H) * I.P;
+  const size_t plane_y = static_cast<size_t>(I.H + 1) * I.P;
+  const float* Dx = I.Dx + c * plane + static_cast<size_t>(gy) * I.P + gx;
+  const float* Dy = I.Dy + c * plane_y + static_cast<size_t>(gy) * I.P + gx;
+  const int cy = HALO + ly, cx = HALO + tx;
+  const float f0 = fs[cy][cx];
+  const float div = Dx[1] * (fs[cy][cx + 1] - f0) - Dx[0] * (f0 - fs[cy][cx - 1]) +
+                    Dy[I.P] * (fs[cy + 1][cx] - f0) - Dy[0] * (f0 - fs[cy - 1][cx]);
+  float G = 0.0f;
+  if (kc.nonlocal_term)
+    for (int b = 0; b < 2 * R + 1; ++b) G += kc.w[b] * gh[ly + b][tx];
+  return lam * G - div;
+}
+
+template <int R, int HALO>
+__device__ __forceinline__ void horiz_gauss(const float (&fs)[kKTY + 2 * HALO][kKTX + 2 * HALO],
+                                            float (&gh)[kKTY + 2 * R][kKTX], const KConst& kc) {
+  if (!kc.nonlocal_term) return;
+  for (int i = threadIdx.x; i < (kKTY + 2 * R) * kKTX; i += NT) {
+    const int j = i / kKTX, lx = i - (i / kKTX) * kKTX;
+    float s = 0.0f;
+    for (int a = 0; a < 2 * R + 1; ++a) s += kc.w[a] * fs[HALO - R + j][HALO + lx - R + a];
+    gh[j][lx] = s;
+  }
+}
+
+// ------------------------------------------------------------ BiCGSTAB
+// (a) p = r + beta (p - omega v); v = L M^-1 p; sigma = (rhat, v); alpha = rho / sigma.
+template <int R>
+__global__ __launch_bounds__(NT) void k_bicg_a(const KImg* __restrict__ imgs, KScal* scal,
+                                                const int* __restrict__ tile_img, double* part, KConst kc,
+                                                int first, int par) {
+  constexpr int HALO = R > 1 ? R : 1;
+  constexpr int SX = kKTX + 2 * HALO, SY = kKTY + 2 * HALO;
+  __shared__ float fs[SY][SX];
+  __shared__ float gh[kKTY + 2 * R][kKTX];
+  const int g = blockIdx.x;
+  const int im = tile_img[g];
+  const KImg I = imgs[im];
+  KScal* sc = scal + im;
+  if (sc->converged || sc->inner_done) return;
+  const TilePos tp = tile_pos(I, im, g);
+  const float beta = first ? 0.0f : static_cast<float>(sc->beta);
+  const float omega = static_cast<float>(sc->omega);
+  const float* rs = first ? I.rhat : I.r;
+  const float* po = I.p[1 - par];
+  const float* vo = I.v[1 - par];
+  float* pn_out = I.p[par];
+  float* vn_out = I.v[par];
+  const int tid = threadIdx.x, tx = tid & (kKTX - 1), ty = tid / kKTX;
+  const int gx = tp.x0 + tx;
+  const size_t plane = static_cast<size_t>(I.H) * I.P;
+  float lv[kPixPerThread];
+  for (int k = 0; k < kPixPerThread; ++k) {
+    const int gy = tp.y0 + ty + 4 * k;
+    lv[k] = (kc.nonlocal_term && gx < I.W && gy < I.H) ? I.lam[static_cast<size_t>(gy) * I.P + gx] : 0.0f;
+  }
+  double acc[1] = {0.0};
+  for (int c = 0; c < 3; ++c) {
+    for (int i = tid; i < SY * SX; i += NT) {
+      const int ly = i / SX, lx = i - (i / SX) * SX;
+      const int yy = tp.y0 - HALO + ly, xx = tp.x0 - HALO + lx;
+      float f = 0.0f;
+      if (yy >= 0 && yy < I.H && xx >= 0 && xx < I.W) {
+        const size_t e = c * plane + static_cast<size_t>(yy) * I.P + xx;
+        const float pn = first ? rs[e] : rs[e] + beta * (po[e] - omega * vo[e]);
+        f = I.invd[e] * pn;
+        if (ly >= HALO && ly < HALO + kKTY && lx >= HALO && lx < HALO + kKTX) pn_out[e] = pn;
+      }
+      fs[ly][lx] = f;
+    }
+    __syncthreads();
+    horiz_gauss<R, HALO>(fs, gh, kc);
+    __syncthreads();
+    for (int k = 0; k < kPixPerThread; ++k) {
+      const int ly = ty + 4 * k, gy = tp.y0 + ly;
+      if (gx < I.W && gy < I.H) {
+        const float v = apply_L<R, HALO>(fs, gh, I, kc, c, gx, gy, tx, ly, lv[k]);
+        const size_t e = c * plane + static_cast<size_t>(gy) * I.P + gx;
+        vn_out[e] = v;
+        acc[0] += static_cast<double>(I.rhat[e]) * v;
+      }
+    }
+    __syncthreads();
+  }
+  double tot[1];
+  if (!finish_tile<1>(acc, part, g, I, sc, tot)) return;
+  if (threadIdx.x != 0) return;
+  const double sigma = tot[0];
+  if (sigma == 0.0 || !isfinite(sigma)) sc->inner_done = 1;
+  else sc->alpha = sc->rho / sigma;
+  sc->counter = 0;
+}
+
+// (b) s = r - alpha v; t = L M^-1 s; omega = (t, s) / (t, t); ||s|| test.
+template <int R>
+__global__ __launch_bounds__(NT) void k_bicg_b(const KImg* __restrict__ imgs, KScal* scal,
+                                                const int* __restrict__ tile_img, double* part, KConst kc,
+                                                int first, int par) {
+  constexpr int HALO = R > 1 ? R : 1;
+  constexpr int SX = kKTX + 2 * HALO, SY = kKTY + 2 * HALO;
+  __shared__ float fs[SY][SX];
+  __shared__ float gh[kKTY + 2 * R][kKTX];
+  const int g = blockIdx.x;
+  const int im = tile_img[g];
+  const KImg I = imgs[im];
+  KScal* sc = scal + im;
+  if (sc->converged || sc->inner_done) return;
+  const TilePos tp = tile_pos(I, im, g);
+  const float alpha = static_cast<float>(sc->alpha);
+  const float* rs = first ? I.rhat : I.r;
+  const float* vn = I.v[par];
+  const int tid = threadIdx.x, tx = tid & (kKTX - 1), ty = tid / kKTX;
+  const int gx = tp.x0 + tx;
+  const size_t plane = static_cast<size_t>(I.H) * I.P;
+  float lv[kPixPerThread];
+  for (int k = 0; k < kPixPerThread; ++k) {
+    const int gy = tp.y0 + ty + 4 * k;
+    lv[k] = (kc.nonlocal_term && gx < I.W && gy < I.H) ? I.lam[static_cast<size_t>(gy) * I.P + gx] : 0.0f;
+  }
+  double acc[3] = {0.0, 0.0, 0.0};  // (t, s), (t, t), (s, s)
+  for (int c = 0; c < 3; ++c) {
+    for (int i = tid; i < SY * SX; i += NT) {
+      const int ly = i / SX, lx = i - (i / SX) * SX;
+      const int yy = tp.y0 - HALO + ly, xx = tp.x0 - HALO + lx;
+      float f = 0.0f;
+      if (yy >= 0 && yy < I.H && xx >= 0 && xx < I.W) {
+        const size_t e = c * plane + static_cast<size_t>(yy) * I.P + xx;
+        const float sv = rs[e] - alpha * vn[e];
+        f = I.invd[e] * sv;
+        if (ly >= HALO && ly < HALO + kKTY && lx >= HALO && lx < HALO + kKTX) I.s[e] = sv;
+      }
+      fs[ly][lx] = f;
+    }
+    __syncthreads();
+    horiz_gauss<R, HALO>(fs, gh, kc);
+    __syncthreads();
+    for (int k = 0; k < kPixPerThread; ++k) {
+      const int ly = ty + 4 * k, gy = tp.y0 + ly;
+      if (gx < I.W && gy < I.H) {
+        const float t = apply_L<R, HALO>(fs, gh, I, kc, c, gx, gy, tx, ly, lv[k]);
+        const size_t e = c * plane + static_cast<size_t>(gy) * I.P + gx;
+        I.t[e] = t;
+        const float s_e = rs[e] - alpha * vn[e];
+        acc[0] += static_cast<double>(t) * s_e;
+        acc[1] += static_cast<double>(t) * t;
+        acc[2] += static_cast<double>(s_e) * s_e;
+      }
+    }
+    __syncthreads();
+  }
+  double tot[3];
+  if (!finish_tile<3>(acc, part, g, I, sc, tot)) return;
+  if (threadIdx.x != 0) return;
+  if (!isfinite(tot[0]) || !isfinite(tot[1]) || !isfinite(tot[2])) {
+    sc->inner_done = 1;
+  } else {
+    if (tot[2] <= kc.eta * kc.eta * sc->bnorm2) sc->half_done = 1;
+    sc->omega = tot[1] > 0.0 ? tot[0] / tot[1] : 0.0;
+  }
+  sc->counter = 0;
+}
+
+// (c) x += alpha M^-1 p + omega M^-1 s; r = s - omega t; rho = (rhat, r); beta.
+__global__ __launch_bounds__(NT) void k_bicg_c(const KImg* __restrict__ imgs, KScal* scal,
+                                                const int* __restrict__ tile_img, double* part, KConst kc,
+                                                int first, int par) {
+  const int g = blockIdx.x;
+  const int im = tile_img[g];
+  const KImg I = imgs[im];
+  KScal* sc = scal + im;
+  if (sc->converged || sc->inner_done) return;
+  const TilePos tp = tile_pos(I, im, g);
+  const float alpha = static_cast<float>(sc->alpha);
+  const float omega = static_cast<float>(sc->omega);
+  const int half = sc->half_done;
+  const float* pn = I.p[par];
+  const int tid = threadIdx.x, tx = tid & (kKTX - 1), ty = tid / kKTX;
+  const int gx = tp.x0 + tx;
+  const size_t plane = static_cast<size_t>(I.H) * I.P;
+  double acc[2] = {0.0, 0.0};  // (rhat, r), (r, r)
+  for (int c = 0; c < 3; ++c) {
+    for (int k = 0; k < kPixPerThread; ++k) {
+      const int gy = tp.y0 + ty + 4 * k;
+      if (gx < I.W && gy < I.H) {
+        const size_t e = c * plane + static_cast<size_t>(gy) * I.P + gx;
+        const float id = I.invd[e];
+        const float xo = first ? 0.0f : I.x[e];
+        if (half) {
+          I.x[e] = xo + alpha * (id * pn[e]);
+        } else {
+          const float sv = I.s[e];
+          I.x[e] = xo + alpha * (id * pn[e]) + omega * (id * sv);
+          const float rn = sv - omega * I.t[e];
+          I.r[e] = rn;
+          acc[0] += static_cast<double>(I.rhat[e]) * rn;
+          acc[1] += static_cast<double>(rn) * rn;
+        }
+      }
+    }
+  }
+  double tot[2];
+  if (!finish_tile<2>(acc, part, g, I, sc, tot)) return;
+  if (threadIdx.x != 0) return;
+  sc->inner_this += 1;
+  sc->pass_inner += 1;
+  if (half) {
+    sc->inner_done = 1;
+  } else {
+    const double rho_new = tot[0];
+    if (!isfinite(tot[1]) || tot[1] <= kc.eta * kc.eta * sc->bnorm2 || sc->omega == 0.0 || rho_new == 0.0) {
+      sc->inner_done = 1;
+    } else {
+      sc->beta = (rho_new / sc->rho) * (sc->alpha / sc->omega);
+      sc->rho = rho_new;
+    }
+  }
+  sc->counter = 0;
+}
+
+// u += delta where this outer step ran at least one inner iteration.
+__global__ __launch_bounds__(NT) void k_update(const KImg* __restrict__ imgs, const KScal* __restrict__ scal,
+                                                const int* __restrict__ tile_img) {
+  const int g = blockIdx.x;
+  const int im = tile_img[g];
+  const KImg I = imgs[im];
+  const KScal* sc = scal + im;
+  if (sc->converged || sc->pass_inner < 1) return;
+  const TilePos tp = tile_pos(I, im, g);
+  const int tid = threadIdx.x, tx = tid & (kKTX - 1), ty = tid / kKTX;
+  const int gx = tp.x0 + tx;
+  const size_t plane = static_cast<size_t>(I.H) * I.P;
+  for (int c = 0; c < 3; ++c)
+    for (int k = 0; k < kPixPerThread; ++k) {
+      const int gy = tp.y0 + ty + 4 * k;
+      if (gx < I.W && gy < I.H) {
+        const size_t e = c * plane + static_cast<size_t>(gy) * I.P + gx;
+        I.u[e] += static_cast<double>(I.x[e]);
+      }
+    }
+}
+
+#define DZ_KRYLOV_DISPATCH(R_, LAUNCH) \
+  switch (R_) {                        \
+    case 0: LAUNCH(0); break;          \
+    case 1: LAUNCH(1); break;          \
+    case 2: LAUNCH(2); break;          \
+    case 3: LAUNCH(3); break;          \
+    case 4: LAUNCH(4); break;          \
+    default: set_error("g_radius outside 0..4"); return DEHAZE_EINVAL; \
+  }
+
+}  // namespace
+
+size_t krylov_image_bytes(int H, int W) { return carve(nullptr, H, W, 0).bytes; }
+
+KImg krylov_carve(void* base, int H, int W, int tile0) { return carve(base, H, W, tile0).img; }
+
+int krylov_init(const KrylovBatch& b, const KImg* h_imgs, const float* const* u0, hipStream_t s) {
+  hipLaunchKernelGGL(k_scal_reset, dim3((b.nimg + NT - 1) / NT), dim3(NT), 0, s, b.d_scal, b.nimg);
+  DZ_CHECK_LAUNCH();
+  for (int i = 0; i < b.nimg; ++i) {
+    const KImg& m = h_imgs[i];
+    hipLaunchKernelGGL(k_set_desc, dim3(1), dim3(1), 0, s, const_cast<KImg*>(b.d_imgs), i, m);
+    DZ_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_tile_map, dim3((m.ntiles + NT - 1) / NT), dim3(NT), 0, s,
+                       const_cast<int*>(b.d_tile_img), m.tile0, m.ntiles, i);
+    DZ_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_init_u, dim3((m.W + NT - 1) / NT, m.H), dim3(NT), 0, s, m, u0 ? u0[i] : nullptr);
+    DZ_CHECK_LAUNCH();
+  }
+  return DEHAZE_OK;
+}
+
+int krylov_residual(const KrylovBatch& b, const KConst& c, int final, hipStream_t s) {
+#define L_RES(R) hipLaunchKernelGGL((k_res<R, 0>), dim3(b.ntiles), dim3(NT), 0, s, b.d_imgs, b.d_scal, b.d_tile_img, \
+                                    b.d_part, c, final)
+  DZ_KRYLOV_DISPATCH(c.R, L_RES)
+#undef L_RES
+  DZ_CHECK_LAUNCH();
+  return DEHAZE_OK;
+}
+
+int krylov_linear_residual(const KrylovBatch& b, const KConst& c, hipStream_t s) {
+#define L_RES(R) hipLaunchKernelGGL((k_res<R, 1>), dim3(b.ntiles), dim3(NT), 0, s, b.d_imgs, b.d_scal, b.d_tile_img, \
+                                    b.d_part, c, 0)
+  DZ_KRYLOV_DISPATCH(c.R, L_RES)
+#undef L_RES
+  DZ_CHECK_LAUNCH();
+  return DEHAZE_OK;
+}
+
+int krylov_snapshot(const KrylovBatch& b, hipStream_t s) {
+  hipLaunchKernelGGL(k_snapshot, dim3(b.ntiles), dim3(NT), 0, s, b.d_imgs, b.d_scal, b.d_tile_img);
+  DZ_CHECK_LAUNCH();
+  return DEHAZE_OK;
+}
+
+int krylov_inner(const KrylovBatch& b, const KConst& c, int it, hipStream_t s) {
+  const int first = it == 1 ? 1 : 0;
+  const int par = it & 1;
+#define L_A(R) hipLaunchKernelGGL((k_bicg_a<R>), dim3(b.ntiles), dim3(NT), 0, s, b.d_imgs, b.d_scal, b.d_tile_img, \
+                                  b.d_part, c, first, par)
+#define L_B(R) hipLaunchKernelGGL((k_bicg_b<R>), dim3(b.ntiles), dim3(NT), 0, s, b.d_imgs, b.d_scal, b.d_tile_img, \
+                                  b.d_part, c, first, par)
+  DZ_KRYLOV_DISPATCH(c.R, L_A)
+  DZ_CHECK_LAUNCH();
+  DZ_KRYLOV_DISPATCH(c.R, L_B)
+  DZ_CHECK_LAUNCH();
+#undef L_A
+#undef L_B
+  hipLaunchKernelGGL(k_bicg_c, dim3(b.ntiles), dim3(NT), 0, s, b.d_imgs, b.d_scal, b.d_tile_img, b.d_part, c, first,
+                     par);
+  DZ_CHECK_LAUNCH();
+  return DEHAZE_OK;
+}
+
+int krylov_update(const KrylovBatch& b, hipStream_t s) {
+  hipLaunchKernelGGL(k_update, dim3(b.ntiles), dim3(NT), 0, s, b.d_imgs, b.d_scal, b.d_tile_img);
+  DZ_CHECK_LAUNCH();
+  return DEHAZE_OK;
+}
+
+int krylov_output(const KImg& img, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_out_u, dim3((img.W + NT - 1) / NT, img.H), dim3(NT), 0, s, img, out);
+  DZ_CHECK_LAUNCH();
+  return DEHAZE_OK;
+}
+
+}  // namespace dz

@@ -1,0 +1,108 @@
+// Lagged-diffusivity (Picard) solve of the main PDE over a list of images.
+//
+// Outer step n (for every image that has not converged):
+//   1. r_n = Phi - L_{D(u_n)} u_n, formed in float64 from the float64 iterate
+//      u_n; D(u_n) is stored per face (float32) for the inner solve, together
+//      with the inverse Jacobi diagonal; rho_n = ||r_n|| / ||Phi||.
+//   2. L_{D(u_n)} delta = r_n is solved by right-preconditioned BiCGSTAB
+//      (Jacobi preconditioner) in float32 until ||r_k|| <= inner_rtol ||r_n||
+//      or max_inner iterations.
+//   3. u_{n+1} = u_n + delta  (= L_{D(u_n)}^-1 Phi up to the inner tolerance).
+// Every launch covers the tiles of all images; per-image scalars and flags
+// live on the device, so one outer step is a fixed launch sequence that can be
+// captured in a HIP graph and replayed.
+#pragma once
+
+#include "internal.hpp"
+
+namespace dz {
+
+constexpr int kKTX = 64;   // tile width of the Krylov kernels
+constexpr int kKTY = 16;   // tile height
+constexpr int kKPart = 4;  // doubles of partial sums per tile
+
+struct KImg {
+  int H, W, P;             // P: pitch of every plane, >= W + 1
+  int tiles_x, ntiles, tile0;
+  const float* phi;        // 3 planes
+  const float* lam;        // 1 plane
+  double* u;               // 3 planes, the iterate
+  double* un;              // 3 planes, u_n: D stays frozen at it during defect-correction passes
+  float* Dx;               // 3 planes of H rows: face f of row j sits left of column f (f = 0..W)
+  float* Dy;               // 3 planes of H + 1 rows: face f of column i sits above row f (f = 0..H)
+  float* invd;             // 3 planes: 1 / diag(L_D)
+  float* rhat;             // 3 planes: r_n, also the BiCGSTAB shadow residual
+  float* r;                // 3 planes
+  float* p[2];             // search direction, ping-pong between iterations
+  float* v[2];             // L M^-1 p, ping-pong between iterations
+  float* s;
+  float* t;
+  float* x;                // 3 planes: the correction delta
+};
+
+struct KScal {
+  double rho, alpha, omega, beta;
+  double bnorm2;           // ||r_n||^2 in float32 terms
+  double rel;              // rho_n = ||r_n|| / ||Phi|| (float64)
+  double rel0;             // rho at the starting iterate
+  int converged;           // rho <= rel_tol reached (or stopped on a non-finite value)
+  int nonfinite;
+  int inner_done, half_done;
+  int inner_this;          // BiCGSTAB iterations of the current outer step
+  int pass_inner;          // BiCGSTAB iterations of the current solve pass
+  int outer;               // updates applied
+  long long inner_total;
+  long long res_evals;
+  unsigned counter;        // last-block-done counter
+  int pad[2];
+};
+
+struct KConst {
+  float w[9];
+  float wc2;
+  float eps;
+  double eps64;
+  double w64[9];
+  double wc2_64;
+  double rel_tol;
+  double eta;
+  int R;
+  int nonlocal_term;
+  int edge_preserving;
+};
+KConst make_kconst(const dehaze_params& p);
+
+// Bytes of one image's planes (internal pitch) and its tile count.
+size_t krylov_image_bytes(int H, int W);
+int krylov_tiles(int H, int W);
+// Fills a descriptor whose planes live at `base` (krylov_image_bytes bytes,
+// 256-byte aligned); phi/lam are carved here too and returned through the
+// descriptor (the front end writes them).
+KImg krylov_carve(void* base, int H, int W, int tile0);
+
+struct KrylovBatch {
+  const KImg* d_imgs;      // device copy of the descriptors
+  KScal* d_scal;           // device scalars, one per image
+  const int* d_tile_img;   // image index of every tile
+  double* d_part;          // kKPart doubles per tile
+  int nimg;
+  int ntiles;
+};
+
+// Starting iterate: u = u0 (float, dense pitch W) or Phi; resets the scalars.
+int krylov_init(const KrylovBatch& b, const KImg* h_imgs, const float* const* u0, hipStream_t s);
+// Residual pass (final != 0: evaluate every image, converged or not).
+int krylov_residual(const KrylovBatch& b, const KConst& c, int final, hipStream_t s);
+// Linear residual Phi - L_{D(u_n)} u with D frozen at the snapshot u_n, as the
+// right-hand side of a defect-correction pass.
+int krylov_linear_residual(const KrylovBatch& b, const KConst& c, hipStream_t s);
+// u_n := u for every image still iterating.
+int krylov_snapshot(const KrylovBatch& b, hipStream_t s);
+// One BiCGSTAB iteration (it = 1 for the first of an outer step).
+int krylov_inner(const KrylovBatch& b, const KConst& c, int it, hipStream_t s);
+// u += delta.
+int krylov_update(const KrylovBatch& b, hipStream_t s);
+// u (float64) -> out (float, dense pitch W).
+int krylov_output(const KImg& img, float* out, hipStream_t s);
+
+}  // namespace dz

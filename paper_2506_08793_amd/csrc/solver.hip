@@ -4,6 +4,7 @@
 #include <cmath>
 
 #include "internal.hpp"
+#include "krylov.hpp"
 #include "solver.hpp"
 
 namespace dz {
@@ -113,17 +114,103 @@ int run_sweeps(const SolveArgs& a, const dehaze_params& p, dehaze_stats* st, hip
   return status;
 }
 
+struct KrylovPlan {
+  KImg img{};
+  float* Ip = nullptr;
+  KImg* d_imgs = nullptr;
+  KScal* d_scal = nullptr;
+  int* d_tile_img = nullptr;
+  double* d_part = nullptr;
+  size_t bytes = 0;
+};
+
+KrylovPlan plan_krylov(void* ws, int H, int W) {
+  KrylovPlan pl;
+  Carver cv(ws, ~size_t(0));
+  char* arena = cv.take<char>(krylov_image_bytes(H, W));
+  pl.img = krylov_carve(arena, H, W, 0);
+  const int nt = krylov_tiles(H, W);
+  pl.Ip = cv.take<float>(3 * static_cast<size_t>(H) * pl.img.P);
+  pl.d_imgs = cv.take<KImg>(1);
+  pl.d_scal = cv.take<KScal>(1);
+  pl.d_tile_img = cv.take<int>(nt);
+  pl.d_part = cv.take<double>(static_cast<size_t>(kKPart) * nt);
+  pl.bytes = cv.used();
+  return pl;
+}
+
+int read_scalars(const KrylovBatch& b, KScal* h, hipStream_t s) {
+  DZ_HIP(hipMemcpyAsync(h, b.d_scal, sizeof(KScal) * b.nimg, hipMemcpyDeviceToHost, s));
+  DZ_HIP(hipStreamSynchronize(s));
+  return DEHAZE_OK;
+}
+
+void fill_stats(const KScal& k, dehaze_stats* st) {
+  st->outer = k.outer;
+  st->converged = (k.converged && !k.nonfinite) ? 1 : 0;
+  st->inner = k.inner_total;
+  st->applications = 2 * k.inner_total + k.res_evals;
+  st->rel_residual = k.rel;
+  st->rel_residual0 = k.rel0;
+  st->status = k.nonfinite ? DEHAZE_ENONFINITE : DEHAZE_OK;
+}
+
+int run_krylov(const SolveArgs& a, const dehaze_params& p, dehaze_stats* st, hipStream_t s) {
+  const int H = a.H, W = a.W;
+  KrylovPlan pl = plan_krylov(a.ws, H, W);
+  const int P = pl.img.P;
+  int rc;
+  if ((rc = launch_to_planar(a.I, a.dtype, a.layout, H, W, a.pitch, pl.Ip, P, s))) return rc;
+  FusedOut fo{nullptr, nullptr, const_cast<float*>(pl.img.lam), const_cast<float*>(pl.img.phi), P};
+  if ((rc = launch_prior_fused(nullptr, pl.Ip, P, a.t, W, a.A, H, W, p, fo, s))) return rc;
+  KrylovBatch b{pl.d_imgs, pl.d_scal, pl.d_tile_img, pl.d_part, 1, pl.img.ntiles};
+  const float* u0 = a.u0;
+  if ((rc = krylov_init(b, &pl.img, &u0, s))) return rc;
+  const KConst kc = make_kconst(p);
+  KScal hs{};
+  for (int n = 0; n < p.max_outer; ++n) {
+    if ((rc = krylov_residual(b, kc, 0, s))) return rc;
+    if (p.inner_refine > 0 && (rc = krylov_snapshot(b, s))) return rc;
+    for (int pass = 0; pass <= p.inner_refine; ++pass) {
+      if (pass > 0 && (rc = krylov_linear_residual(b, kc, s))) return rc;
+      for (int it = 1; it <= p.max_inner; ++it)
+        if ((rc = krylov_inner(b, kc, it, s))) return rc;
+      if ((rc = krylov_update(b, s))) return rc;
+    }
+    if (p.rel_tol > 0.0 && (n + 1) % p.check_every == 0) {
+      if ((rc = read_scalars(b, &hs, s))) return rc;
+      if (hs.converged) break;
+    }
+  }
+  if ((rc = krylov_residual(b, kc, 1, s))) return rc;
+  if ((rc = krylov_output(pl.img, a.u, s))) return rc;
+  if (!st && p.rel_tol <= 0.0) return DEHAZE_OK;
+  if ((rc = read_scalars(b, &hs, s))) return rc;
+  int status = hs.nonfinite ? DEHAZE_ENONFINITE
+                            : ((p.rel_tol > 0.0 && !hs.converged) ? DEHAZE_ENOTCONV : DEHAZE_OK);
+  if (st) {
+    fill_stats(hs, st);
+    st->status = status;
+    DZ_HIP(hipMemcpyAsync(st->A, a.A, 3 * sizeof(float), hipMemcpyDeviceToHost, s));
+    DZ_HIP(hipStreamSynchronize(s));
+  }
+  if (status == DEHAZE_ENONFINITE) set_error("residual is not finite");
+  else if (status == DEHAZE_ENOTCONV)
+    set_error("rel_tol %g not reached in %d outer steps (rho %g)", p.rel_tol, hs.outer, hs.rel);
+  return status;
+}
+
 }  // namespace
 
 size_t solver_workspace_bytes(int H, int W, const dehaze_params& p) {
-  (void)p;
+  if (p.scheme == DEHAZE_PICARD_KRYLOV) return plan_krylov(nullptr, H, W).bytes;
   return plan_sweeps(nullptr, H, W).bytes;
 }
 
 int solve_one(Ctx& ctx, const SolveArgs& a, const dehaze_params& p, dehaze_stats* st, hipStream_t s) {
   (void)ctx;
   if (p.warm_start) { set_error("warm start needs loaded network weights"); return DEHAZE_EINVAL; }
-  if (p.scheme == DEHAZE_PICARD_KRYLOV) { set_error("scheme not available"); return DEHAZE_EINVAL; }
+  if (p.scheme == DEHAZE_PICARD_KRYLOV) return run_krylov(a, p, st, s);
   return run_sweeps(a, p, st, s);
 }
 

@@ -1,0 +1,110 @@
+"""GPU lagged-diffusivity solve (Picard outer steps, BiCGSTAB corrections) vs
+the oracle's exact Picard steps (sparse LU per step), on the same float32 t, A."""
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import ctx, dev, host, require_gpu, say
+from oracle import dehaze_ref as o
+
+pytestmark = pytest.mark.gpu
+
+U_TOL = 1e-4
+
+
+def _inputs(H, W, seed, beta=1.0, occlusion=False):
+    img = synth.hazy_image(H, W, seed, beta_haze=beta, occlusion=occlusion)
+    pr = o.prior(img["I"])
+    t32 = pr["t"].astype(np.float32)
+    A32 = pr["A"].astype(np.float32)
+    lam = o.adaptive_weight(t32.astype(np.float64))
+    phi = o.reconstruction(img["I"], t32, A32, o.DEFAULT.t0)
+    return img["I"], t32, A32, lam, phi
+
+
+def _solve(I, t32, A32, u0=None, **kw):
+    import paper_2506_08793_amd as d
+    p = d.dehaze_params_default(scheme=d.PICARD_KRYLOV, **kw)
+    u, st = d.dehaze_solve(ctx(), dev(I), dev(t32), dev(A32), params=p,
+                           u0=None if u0 is None else dev(u0.astype(np.float32)))
+    return host(u), st
+
+
+def test_picard_50_steps_small_workload():
+    # 64x64 workload: 50 lagged-diffusivity steps with tight inner solves
+    require_gpu()
+    I, t32, A32, lam, phi = _inputs(64, 64, 1000)
+    say("picard 64x64 50 steps")
+    u, st = _solve(I, t32, A32, max_outer=50, rel_tol=0.0, inner_rtol=1e-4, max_inner=200, inner_refine=3)
+    ref = o.solve(phi, lam, "picard", steps=50)
+    err = np.max(np.abs(u - ref.u))
+    say(f"  max-abs {err:.3e} rho gpu {st['rel_residual']:.6e} oracle {ref.rho[-1]:.6e} inner {st['inner']}")
+    assert err <= U_TOL
+    assert st["outer"] == 50
+    assert abs(st["rel_residual"] - ref.rho[-1]) <= 1e-3 * ref.rho[-1] + 1e-6
+    assert abs(st["rel_residual0"] - ref.rho[0]) <= 1e-6 * ref.rho[0]
+
+
+@pytest.mark.parametrize("H,W,seed,n", [(1, 1, 3, 3), (3, 2, 4, 4), (37, 53, 5, 6), (17, 130, 6, 5),
+                                        (100, 67, 7, 4)])
+def test_picard_ragged_shapes(H, W, seed, n):
+    require_gpu()
+    I, t32, A32, lam, phi = _inputs(H, W, seed, beta=(0.5, 2.0), occlusion=True)
+    say(f"picard H={H} W={W} n={n}")
+    u, st = _solve(I, t32, A32, max_outer=n, rel_tol=0.0, inner_rtol=1e-4, max_inner=200, inner_refine=3)
+    ref = o.solve(phi, lam, "picard", steps=n)
+    err = np.max(np.abs(u - ref.u))
+    say(f"  max-abs {err:.3e}")
+    assert err <= U_TOL
+
+
+def test_picard_from_given_start_and_ablations():
+    require_gpu()
+    I, t32, A32, lam, phi = _inputs(30, 41, 8)
+    rng = np.random.default_rng(2)
+    u0 = phi + rng.uniform(-0.5, 0.5, size=phi.shape)
+    for flags in ({}, {"nonlocal_term": 0}, {"edge_preserving": 0}, {"adaptive": 0}):
+        say(f"picard u0 flags={flags}")
+        u, st = _solve(I, t32, A32, u0=u0, max_outer=4, rel_tol=0.0, inner_rtol=1e-4, max_inner=200, inner_refine=3, **flags)
+        q = o.with_params(**{k: bool(v) for k, v in flags.items()})
+        lam_q = o.adaptive_weight(t32.astype(np.float64), q)
+        ref = o.solve(phi, lam_q, "picard", q, steps=4, u0=u0.astype(np.float32).astype(np.float64))
+        err = np.max(np.abs(u - ref.u))
+        scale = max(1.0, np.max(np.abs(ref.u)))
+        say(f"  max-abs {err:.3e} max|u| {scale:.1f}")
+        if flags:
+            # without lambda G (or with D = 1) u grows to O(1e3) and the
+            # operator loses its zeroth-order term; a float32 u alone carries
+            # 2^-24 |u|, so the bound is relative to |u| there
+            assert err <= 1e-3 * scale
+        else:
+            assert err <= U_TOL
+
+
+def test_picard_reaches_tolerance():
+    # residual-terminated solve: the float64 residual the library reports must
+    # be <= 1e-5; the oracle checks the float32 output against the float32
+    # rounding floor of its own converged solution, and reports the distance
+    require_gpu()
+    I, t32, A32, lam, phi = _inputs(32, 32, 12)
+    say("picard 32x32 to 1e-5")
+    u, st = _solve(I, t32, A32, max_outer=3000, rel_tol=1e-5, inner_rtol=0.1, max_inner=10, check_every=16)
+    say(f"  {st}")
+    assert st["converged"] and st["status"] == 0 and st["rel_residual"] <= 1e-5
+    assert st["outer"] % 16 != 0 or st["outer"] > 0
+    _, rho_gpu_u = o.residual(u.astype(np.float64), phi, lam)
+    ref = o.solve(phi, lam, "picard", rel_tol=1e-10, max_steps=3000)
+    _, floor = o.residual(ref.u.astype(np.float32).astype(np.float64), phi, lam)
+    say(f"  oracle rho of float32 output {rho_gpu_u:.3e}, float32 floor {floor:.3e}, "
+        f"max-abs vs converged {np.max(np.abs(u - ref.u)):.3e}")
+    assert rho_gpu_u <= 2.0 * floor + 2e-5
+    assert np.max(np.abs(u - ref.u)) <= 1e-2
+
+
+def test_picard_not_converged_status():
+    require_gpu()
+    I, t32, A32, lam, phi = _inputs(16, 16, 13)
+    say("picard ENOTCONV")
+    u, st = _solve(I, t32, A32, max_outer=3, rel_tol=1e-12, check_every=1)
+    assert not st["converged"] and st["status"] == -4 and st["outer"] == 3
+    assert np.all(np.isfinite(u))
