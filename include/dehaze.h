@@ -171,6 +171,36 @@ int dehaze_solve(dehaze_ctx* ctx, const void* I, int dtype, int layout, int H, i
                  const float* t, const float* A, const dehaze_params* p, const float* u0,
                  float* u, void* ws, size_t ws_bytes, dehaze_stats* stats, void* stream);
 
+/* ------------------------------------------------------------ batch solve
+ * Many images of uneven size solved together by the lagged-diffusivity
+ * scheme (DEHAZE_PICARD_KRYLOV only): every kernel launch covers the tiles of
+ * all images still iterating, the per-image reductions and stopping tests run
+ * on the device, and groups of check_every outer steps are captured once in a
+ * HIP graph and replayed until every image reaches rel_tol (or max_outer).
+ * Per image, t and A are taken as given or, when NULL, estimated by the
+ * front end of dehaze_prior (Section II-D); lambda(t) and Phi follow
+ * (Sections II-A, II-D).  The call synchronises `stream` when rel_tol > 0
+ * or stats is non-NULL.  stats (host, n entries, nullable) receives each
+ * image's counts, residuals, A and status.  Returns DEHAZE_OK, or the worst
+ * per-image status (DEHAZE_ENONFINITE before DEHAZE_ENOTCONV), or an error.
+ * The context keeps the captured graph for reuse by a later call with the
+ * same workspace, batch layout and parameters. */
+typedef struct dehaze_image {
+  const void* I;        /* image (the call's dtype and layout) */
+  int32_t H, W, pitch;  /* size and pitch in pixels, pitch >= W */
+  int32_t reserved;     /* must be zero */
+  float* u;             /* output: planar, pitch W */
+  const float* t;       /* H x W transmission, or NULL to estimate it */
+  const float* A;       /* 3 device floats, or NULL to estimate them */
+  const float* u0;      /* starting iterate (planar, pitch W), or NULL for Phi */
+  float* t_out;         /* nullable: receives the estimated t (H x W) */
+  float* A_out;         /* nullable: receives the estimated A (3 floats) */
+} dehaze_image;
+
+size_t dehaze_batch_workspace_size(int n, const dehaze_image* imgs, const dehaze_params* p);
+int dehaze_batch(dehaze_ctx* ctx, int n, const dehaze_image* imgs, int dtype, int layout,
+                 const dehaze_params* p, void* ws, size_t ws_bytes, dehaze_stats* stats, void* stream);
+
 /* ------------------------------------------------------------ residual
  * rho = ||Phi - L_{D(u)} u||_2 / ||Phi||_2 over all channels, for planar
  * u, phi (pitch W) and lam (H x W): the quantity the main PDE sets to zero.

@@ -5,5 +5,5 @@ binding.  Import fails if the library has not been built.
 """
 from .binding import (  # noqa: F401
     CHW, EXPORTED, HWC, JACOBI, PAPER_EXPLICIT, PICARD_KRYLOV, U8, F32, Context, DehazeError, Params,
-    Stats, dehaze_params_default, dehaze_prior, dehaze_residual, dehaze_solve, solve_workspace,
+    Stats, Image, batch_workspace_bytes, dehaze_batch, dehaze_params_default, dehaze_prior, dehaze_residual, dehaze_solve, solve_workspace,
 )

@@ -57,6 +57,14 @@ class Stats(ctypes.Structure):
                 "rel_residual0": self.rel_residual0, "A": list(self.A), "status": self.status}
 
 
+class Image(ctypes.Structure):
+    _fields_ = [
+        ("I", c_void_p), ("H", c_int32), ("W", c_int32), ("pitch", c_int32), ("reserved", c_int32),
+        ("u", c_void_p), ("t", c_void_p), ("A", c_void_p), ("u0", c_void_p), ("t_out", c_void_p),
+        ("A_out", c_void_p),
+    ]
+
+
 class DehazeError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"{msg} (code {code})")
@@ -64,7 +72,7 @@ class DehazeError(RuntimeError):
 
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2506_08793_amd.build`")
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_2506_08793_amd/build.py`")
 
 _lib = ctypes.CDLL(LIB_PATH)
 _P = POINTER(Params)
@@ -85,6 +93,8 @@ _SIGS = {
     "dehaze_solve_workspace_size": (c_size_t, [c_int, c_int, _P]),
     "dehaze_solve": (c_int, [c_void_p, c_void_p, c_int, c_int, c_int, c_int, c_int, c_void_p, c_void_p, _P,
                              c_void_p, c_void_p, c_void_p, c_size_t, _S, c_void_p]),
+    "dehaze_batch_workspace_size": (c_size_t, [c_int, POINTER(Image), _P]),
+    "dehaze_batch": (c_int, [c_void_p, c_int, POINTER(Image), c_int, c_int, _P, c_void_p, c_size_t, _S, c_void_p]),
     "dehaze_residual_workspace_size": (c_size_t, [c_int, c_int, _P]),
     "dehaze_residual": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, _P, c_void_p,
                                 POINTER(c_double), c_void_p, c_size_t, c_void_p]),
@@ -230,3 +240,55 @@ def dehaze_residual(ctx: Context, u: torch.Tensor, phi: torch.Tensor, lam: torch
     _check(_lib.dehaze_residual(ctx.handle, u.data_ptr(), phi.data_ptr(), lam.data_ptr(), H, W, ctypes.byref(p),
                                 _ptr(r), ctypes.byref(rho), ws.data_ptr(), ws.numel(), _stream()))
     return rho.value, r
+
+
+def dehaze_batch(ctx: Context, images, params: Params = None, layout: str = "CHW", t=None, A=None, u0=None,
+                 want_t: bool = False, stats: bool = True, ws: torch.Tensor = None, outs=None):
+    """Solve a list of device images (each CHW (3,H,W) or HWC (H,W,3), one dtype).
+
+    t, A, u0: optional per-image lists (None entries are estimated / Phi).
+    Returns (list of u, list of stats dicts or None, list of t or None, list of A).
+    """
+    p = params or dehaze_params_default()
+    n = len(images)
+    arr = (Image * n)()
+    keep = []
+    us, ts, As = [], [], []
+    dtype0 = None
+    for i, I in enumerate(images):
+        dtype, lay, H, W, pitch = _image_args(I, layout)
+        if dtype0 is None:
+            dtype0, lay0 = dtype, lay
+        elif dtype != dtype0:
+            raise ValueError("all images of a batch share one dtype")
+        u = outs[i] if outs is not None else torch.empty((3, H, W), dtype=torch.float32, device=I.device)
+        ti = None if t is None else t[i]
+        Ai = None if A is None else A[i]
+        ui = None if u0 is None else u0[i]
+        t_out = torch.empty((H, W), dtype=torch.float32, device=I.device) if (want_t and ti is None) else None
+        A_out = torch.empty(3, dtype=torch.float32, device=I.device) if Ai is None else None
+        arr[i] = Image(I.data_ptr(), H, W, pitch, 0, u.data_ptr(), _ptr(ti), _ptr(Ai), _ptr(ui), _ptr(t_out),
+                       _ptr(A_out))
+        keep += [ti, Ai, ui]
+        us.append(u)
+        ts.append(t_out if ti is None else ti)
+        As.append(A_out if Ai is None else Ai)
+    need = _lib.dehaze_batch_workspace_size(n, arr, ctypes.byref(p))
+    if need == 0:
+        raise DehazeError(EINVAL, "bad batch description")
+    if ws is None or ws.numel() < need:
+        ws = _workspace(need, images[0].device)
+    st = (Stats * n)() if stats else None
+    rc = _lib.dehaze_batch(ctx.handle, n, arr, dtype0, lay0, ctypes.byref(p), ws.data_ptr(), ws.numel(),
+                           st if st is not None else None, _stream())
+    _check(rc, allow=(OK, ENOTCONV))
+    return us, ([x.as_dict() for x in st] if st is not None else None), ts, As
+
+
+def batch_workspace_bytes(shapes, params: Params = None) -> int:
+    p = params or dehaze_params_default()
+    n = len(shapes)
+    arr = (Image * n)()
+    for i, (H, W) in enumerate(shapes):
+        arr[i] = Image(1, H, W, W, 0, 1, None, None, None, None, None)
+    return int(_lib.dehaze_batch_workspace_size(n, arr, ctypes.byref(p)))

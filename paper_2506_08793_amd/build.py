@@ -1,6 +1,7 @@
 """Build libdehaze.so (all HIP sources of csrc/) for gfx950 with hipcc.
 
-Usage: python -m paper_2506_08793_amd.build   (or call build())
+Usage: python paper_2506_08793_amd/build.py   (or call build()); run it by path so that
+the package, which loads the library, is not imported before the build.
 The library is written next to this file, so it travels with the source tree.
 """
 from __future__ import annotations

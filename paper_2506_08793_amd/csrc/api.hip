@@ -72,16 +72,7 @@ struct PriorPlan {
 
 static PriorPlan plan_prior(void* ws, int H, int W) {
   PriorPlan pl;
-  const int P = padded_pitch(W);
-  const size_t plane = static_cast<size_t>(H) * P;
-  Carver cv(ws, ~size_t(0));
-  pl.b.P = P;
-  pl.b.Ip = cv.take<float>(3 * plane);
-  pl.b.mrow = cv.take<float>(3 * plane);
-  pl.b.m = cv.take<float>(3 * plane);
-  pl.b.dc = cv.take<float>(plane);
-  pl.b.sel = cv.take<char>(prior_scratch_bytes(H, W));
-  pl.bytes = cv.used();
+  pl.bytes = carve_prior(ws, H, W, &pl.b);
   return pl;
 }
 
@@ -192,7 +183,7 @@ int dehaze_prior(dehaze_ctx* ctx, const void* I, int dtype, int layout, int H, i
   } else {
     if ((rc = launch_airlight(pl.b, H, W, p->atm_divisor, A_out, s))) return rc;
   }
-  FusedOut o{t_d, t, lam, phi, W};
+  FusedOut o{t_d, t, lam, phi, W, W};
   return launch_prior_fused(pl.b.m, pl.b.Ip, pl.b.P, nullptr, 0, A, H, W, *p, o, s);
 }
 
@@ -218,6 +209,42 @@ int dehaze_solve(dehaze_ctx* ctx, const void* I, int dtype, int layout, int H, i
   DZ_HIP(hipSetDevice(ctx->c.device));
   SolveArgs a{I, dtype, layout, H, W, pitch, t, A, u0, u, ws, ws_bytes};
   return solve_one(ctx->c, a, *p, stats, static_cast<hipStream_t>(stream));
+}
+
+static int check_batch(int n, const dehaze_image* imgs) {
+  if (n < 1 || !imgs) { set_error("batch needs n >= 1 images"); return DEHAZE_EINVAL; }
+  for (int i = 0; i < n; ++i) {
+    const dehaze_image& m = imgs[i];
+    if (!m.I || !m.u) { set_error("image %d: I and u are required", i); return DEHAZE_EINVAL; }
+    if (m.H < 1 || m.W < 1 || m.pitch < m.W) { set_error("image %d: bad size %d x %d pitch %d", i, m.H, m.W, m.pitch); return DEHAZE_EINVAL; }
+    if (static_cast<long long>(m.H) * m.W > (1LL << 30)) { set_error("image %d too large", i); return DEHAZE_EINVAL; }
+  }
+  return DEHAZE_OK;
+}
+
+size_t dehaze_batch_workspace_size(int n, const dehaze_image* imgs, const dehaze_params* p) {
+  (void)p;
+  if (check_batch(n, imgs)) return 0;
+  return batch_workspace_bytes(n, imgs);
+}
+
+int dehaze_batch(dehaze_ctx* ctx, int n, const dehaze_image* imgs, int dtype, int layout, const dehaze_params* p,
+                 void* ws, size_t ws_bytes, dehaze_stats* stats, void* stream) {
+  clear_error();
+  if (!ctx) { set_error("ctx is NULL"); return DEHAZE_EINVAL; }
+  int rc = check_params(p);
+  if (rc) return rc;
+  if ((rc = check_batch(n, imgs))) return rc;
+  if (dtype != DEHAZE_U8 && dtype != DEHAZE_F32) { set_error("unknown dtype %d", dtype); return DEHAZE_EINVAL; }
+  if (layout != DEHAZE_HWC && layout != DEHAZE_CHW) { set_error("unknown layout %d", layout); return DEHAZE_EINVAL; }
+  if (p->scheme != DEHAZE_PICARD_KRYLOV) { set_error("the batch solve runs DEHAZE_PICARD_KRYLOV only"); return DEHAZE_EINVAL; }
+  const size_t need = batch_workspace_bytes(n, imgs);
+  if (!ws || ws_bytes < need) {
+    set_error("batch workspace needs %zu bytes, got %zu", need, ws_bytes);
+    return DEHAZE_ENOMEM;
+  }
+  DZ_HIP(hipSetDevice(ctx->c.device));
+  return solve_batch(ctx->c, n, imgs, dtype, layout, *p, ws, stats, static_cast<hipStream_t>(stream));
 }
 
 size_t dehaze_residual_workspace_size(int H, int W, const dehaze_params* p) {

@@ -55,10 +55,12 @@ struct Carver {
 };
 
 // ---------------------------------------------------------------- context
+struct GraphCache;  // captured outer-step graphs (solver.hip)
 struct Ctx {
   int device = 0;
   int num_cus = 256;
   int lds_bytes = 65536;
+  GraphCache* graphs = nullptr;
 };
 
 // ---------------------------------------------------------------- launchers
@@ -79,6 +81,9 @@ struct PriorBufs {
   int P;
 };
 size_t prior_scratch_bytes(int H, int W);
+// Carves the front-end buffers for an H x W image out of `ws` (nullptr: size
+// only); returns the bytes used.
+size_t carve_prior(void* ws, int H, int W, PriorBufs* b);
 int launch_patch_min(const void* I, int dtype, int layout, int H, int W, int pitch, int patch,
                      const PriorBufs& b, float* dark, uint8_t* dark_u8, hipStream_t s);
 // Dark-channel-prior airlight; writes A_out[3] (device).
@@ -87,7 +92,8 @@ int launch_airlight(const PriorBufs& b, int H, int W, int atm_divisor, float* A_
 // given t) and A.  All outputs nullable; strided outputs use pitch `op`.
 struct FusedOut {
   float* t_d; float* t; float* lam; float* phi;
-  int op;          // pitch of t_d, t, lam, phi (elements)
+  int op;          // pitch of lam and phi (elements)
+  int tp;          // pitch of t_d and t (elements)
 };
 int launch_prior_fused(const float* m, const float* Ip, int P, const float* t_in, int t_pitch,
                        const float* A, int H, int W, const dehaze_params& p,

@@ -442,11 +442,11 @@ __global__ __launch_bounds__(256) void k_prior_fused(const float* __restrict__ m
     const float q1 = static_cast<float>(static_cast<double>(m[plane + e]) / a1);
     const float q2 = static_cast<float>(static_cast<double>(m[2 * plane + e]) / a2);
     const float td = fminf(fminf(q0, q1), q2);
-    if (o.t_d) o.t_d[oe] = td;
+    if (o.t_d) o.t_d[static_cast<size_t>(y) * o.tp + x] = td;
     double t = 1.0 - fp.omega * static_cast<double>(td);
     t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
     t32 = static_cast<float>(t);
-    if (o.t) o.t[oe] = t32;
+    if (o.t) o.t[static_cast<size_t>(y) * o.tp + x] = t32;
   } else {
     t32 = t_in[static_cast<size_t>(y) * t_pitch + x];
   }
@@ -480,6 +480,19 @@ int sel_chunks(int H, int W) {
 }
 
 }  // namespace
+
+size_t carve_prior(void* ws, int H, int W, PriorBufs* b) {
+  const int P = padded_pitch(W);
+  const size_t plane = static_cast<size_t>(H) * P;
+  Carver cv(ws, ~size_t(0));
+  b->P = P;
+  b->Ip = cv.take<float>(3 * plane);
+  b->mrow = cv.take<float>(3 * plane);
+  b->m = cv.take<float>(3 * plane);
+  b->dc = cv.take<float>(plane);
+  b->sel = cv.take<char>(prior_scratch_bytes(H, W));
+  return cv.used();
+}
 
 size_t prior_scratch_bytes(int H, int W) {
   const int nch = sel_chunks(H, W);

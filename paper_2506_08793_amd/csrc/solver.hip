@@ -1,7 +1,10 @@
 // One-image solve: builds lambda(t) and Phi(I, t, A) (Sections II-A, II-D),
 // picks the starting iterate and runs the chosen fixed-point iteration
 // (Appendix A-1) with its stopping rule.
+#include <algorithm>
 #include <cmath>
+#include <cstring>
+#include <vector>
 
 #include "internal.hpp"
 #include "krylov.hpp"
@@ -57,7 +60,7 @@ int run_sweeps(const SolveArgs& a, const dehaze_params& p, dehaze_stats* st, hip
   SweepPlan pl = plan_sweeps(a.ws, H, W);
   int rc;
   if ((rc = launch_to_planar(a.I, a.dtype, a.layout, H, W, a.pitch, pl.Ip, pl.P, s))) return rc;
-  FusedOut fo{nullptr, nullptr, pl.lam, pl.phi, pl.P};
+  FusedOut fo{nullptr, nullptr, pl.lam, pl.phi, pl.P, pl.P};
   if ((rc = launch_prior_fused(nullptr, pl.Ip, pl.P, a.t, W, a.A, H, W, p, fo, s))) return rc;
   if (a.u0) rc = launch_copy3(a.u0, W, pl.ua, pl.P, H, W, s);
   else rc = launch_copy3(pl.phi, pl.P, pl.ua, pl.P, H, W, s);
@@ -155,39 +158,136 @@ void fill_stats(const KScal& k, dehaze_stats* st) {
   st->status = k.nonfinite ? DEHAZE_ENONFINITE : DEHAZE_OK;
 }
 
-int run_krylov(const SolveArgs& a, const dehaze_params& p, dehaze_stats* st, hipStream_t s) {
+// One lagged-diffusivity step for every image still iterating.
+int outer_step(const KrylovBatch& b, const KConst& kc, const dehaze_params& p, hipStream_t s) {
+  int rc;
+  if ((rc = krylov_residual(b, kc, 0, s))) return rc;
+  if (p.inner_refine > 0 && (rc = krylov_snapshot(b, s))) return rc;
+  for (int pass = 0; pass <= p.inner_refine; ++pass) {
+    if (pass > 0 && (rc = krylov_linear_residual(b, kc, s))) return rc;
+    for (int it = 1; it <= p.max_inner; ++it)
+      if ((rc = krylov_inner(b, kc, it, s))) return rc;
+    if ((rc = krylov_update(b, s))) return rc;
+  }
+  return DEHAZE_OK;
+}
+
+}  // namespace
+
+// A captured group of `steps` outer steps, replayed until the images converge.
+// The key holds everything the captured kernel arguments depend on.
+struct GraphCache {
+  hipStream_t cap = nullptr;
+  hipGraphExec_t exec = nullptr;
+  KrylovBatch b{};
+  KConst kc{};
+  int steps = 0, max_inner = 0, refine = 0;
+};
+
+namespace {
+
+bool same_key(const GraphCache& g, const KrylovBatch& b, const KConst& kc, int steps, const dehaze_params& p) {
+  return g.exec && g.b.d_imgs == b.d_imgs && g.b.d_scal == b.d_scal && g.b.d_tile_img == b.d_tile_img &&
+         g.b.d_part == b.d_part && g.b.nimg == b.nimg && g.b.ntiles == b.ntiles && g.steps == steps &&
+         g.max_inner == p.max_inner && g.refine == p.inner_refine && std::memcmp(&g.kc, &kc, sizeof(kc)) == 0;
+}
+
+int graph_for(Ctx& ctx, const KrylovBatch& b, const KConst& kc, int steps, const dehaze_params& p,
+              hipGraphExec_t* out) {
+  if (!ctx.graphs) ctx.graphs = new GraphCache();
+  GraphCache& g = *ctx.graphs;
+  if (same_key(g, b, kc, steps, p)) {
+    *out = g.exec;
+    return DEHAZE_OK;
+  }
+  if (g.exec) {
+    DZ_HIP(hipGraphExecDestroy(g.exec));
+    g.exec = nullptr;
+  }
+  if (!g.cap) DZ_HIP(hipStreamCreateWithFlags(&g.cap, hipStreamNonBlocking));
+  DZ_HIP(hipStreamBeginCapture(g.cap, hipStreamCaptureModeThreadLocal));
+  int rc = DEHAZE_OK;
+  for (int i = 0; i < steps && rc == DEHAZE_OK; ++i) rc = outer_step(b, kc, p, g.cap);
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(g.cap, &graph);
+  if (rc) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  if (e != hipSuccess) {
+    set_error("graph capture failed: %s", hipGetErrorString(e));
+    return DEHAZE_EHIP;
+  }
+  const hipError_t ei = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ei != hipSuccess) {
+    g.exec = nullptr;
+    set_error("graph instantiation failed: %s", hipGetErrorString(ei));
+    return DEHAZE_EHIP;
+  }
+  g.b = b;
+  g.kc = kc;
+  g.steps = steps;
+  g.max_inner = p.max_inner;
+  g.refine = p.inner_refine;
+  *out = g.exec;
+  return DEHAZE_OK;
+}
+
+// Runs outer steps (groups of check_every, replayed from a HIP graph) until
+// every image has converged or max_outer steps were taken, then evaluates the
+// final residual.  h (nimg entries) receives the scalars when they are read.
+int krylov_loop(Ctx& ctx, const KrylovBatch& b, const dehaze_params& p, KScal* h, bool need_scalars,
+                hipStream_t s) {
+  const KConst kc = make_kconst(p);
+  const int per = std::max(1, std::min(p.check_every, p.max_outer));
+  hipGraphExec_t exec = nullptr;
+  int rc;
+  if (p.max_outer >= per && (rc = graph_for(ctx, b, kc, per, p, &exec))) return rc;
+  int done = 0;
+  while (done < p.max_outer) {
+    const int k = std::min(per, p.max_outer - done);
+    if (k == per && exec) {
+      DZ_HIP(hipGraphLaunch(exec, s));
+    } else {
+      for (int i = 0; i < k; ++i)
+        if ((rc = outer_step(b, kc, p, s))) return rc;
+    }
+    done += k;
+    if (p.rel_tol > 0.0) {
+      if ((rc = read_scalars(b, h, s))) return rc;
+      bool all = true;
+      for (int i = 0; i < b.nimg; ++i) all = all && h[i].converged;
+      if (all) break;
+    }
+  }
+  if ((rc = krylov_residual(b, kc, 1, s))) return rc;
+  if (need_scalars || p.rel_tol > 0.0) return read_scalars(b, h, s);
+  return DEHAZE_OK;
+}
+
+int image_status(const KScal& k, const dehaze_params& p) {
+  if (k.nonfinite) return DEHAZE_ENONFINITE;
+  if (p.rel_tol > 0.0 && !k.converged) return DEHAZE_ENOTCONV;
+  return DEHAZE_OK;
+}
+
+int run_krylov(Ctx& ctx, const SolveArgs& a, const dehaze_params& p, dehaze_stats* st, hipStream_t s) {
   const int H = a.H, W = a.W;
   KrylovPlan pl = plan_krylov(a.ws, H, W);
   const int P = pl.img.P;
   int rc;
   if ((rc = launch_to_planar(a.I, a.dtype, a.layout, H, W, a.pitch, pl.Ip, P, s))) return rc;
-  FusedOut fo{nullptr, nullptr, const_cast<float*>(pl.img.lam), const_cast<float*>(pl.img.phi), P};
+  FusedOut fo{nullptr, nullptr, const_cast<float*>(pl.img.lam), const_cast<float*>(pl.img.phi), P, P};
   if ((rc = launch_prior_fused(nullptr, pl.Ip, P, a.t, W, a.A, H, W, p, fo, s))) return rc;
   KrylovBatch b{pl.d_imgs, pl.d_scal, pl.d_tile_img, pl.d_part, 1, pl.img.ntiles};
   const float* u0 = a.u0;
   if ((rc = krylov_init(b, &pl.img, &u0, s))) return rc;
-  const KConst kc = make_kconst(p);
   KScal hs{};
-  for (int n = 0; n < p.max_outer; ++n) {
-    if ((rc = krylov_residual(b, kc, 0, s))) return rc;
-    if (p.inner_refine > 0 && (rc = krylov_snapshot(b, s))) return rc;
-    for (int pass = 0; pass <= p.inner_refine; ++pass) {
-      if (pass > 0 && (rc = krylov_linear_residual(b, kc, s))) return rc;
-      for (int it = 1; it <= p.max_inner; ++it)
-        if ((rc = krylov_inner(b, kc, it, s))) return rc;
-      if ((rc = krylov_update(b, s))) return rc;
-    }
-    if (p.rel_tol > 0.0 && (n + 1) % p.check_every == 0) {
-      if ((rc = read_scalars(b, &hs, s))) return rc;
-      if (hs.converged) break;
-    }
-  }
-  if ((rc = krylov_residual(b, kc, 1, s))) return rc;
+  if ((rc = krylov_loop(ctx, b, p, &hs, st != nullptr, s))) return rc;
   if ((rc = krylov_output(pl.img, a.u, s))) return rc;
   if (!st && p.rel_tol <= 0.0) return DEHAZE_OK;
-  if ((rc = read_scalars(b, &hs, s))) return rc;
-  int status = hs.nonfinite ? DEHAZE_ENONFINITE
-                            : ((p.rel_tol > 0.0 && !hs.converged) ? DEHAZE_ENOTCONV : DEHAZE_OK);
+  const int status = image_status(hs, p);
   if (st) {
     fill_stats(hs, st);
     st->status = status;
@@ -200,6 +300,78 @@ int run_krylov(const SolveArgs& a, const dehaze_params& p, dehaze_stats* st, hip
   return status;
 }
 
+// ------------------------------------------------------------ batch
+struct BatchPlan {
+  char* prior_ws = nullptr;
+  std::vector<KImg> imgs;
+  std::vector<float*> t_int;
+  std::vector<float*> A_int;
+  KImg* d_imgs = nullptr;
+  KScal* d_scal = nullptr;
+  int* d_tile_img = nullptr;
+  double* d_part = nullptr;
+  int ntiles = 0;
+  size_t bytes = 0;
+};
+
+BatchPlan plan_batch(void* ws, int n, const dehaze_image* im) {
+  BatchPlan pl;
+  Carver cv(ws, ~size_t(0));
+  size_t prior_max = 0;
+  for (int i = 0; i < n; ++i) {
+    PriorBufs tmp{};
+    prior_max = std::max(prior_max, carve_prior(nullptr, im[i].H, im[i].W, &tmp));
+  }
+  pl.prior_ws = cv.take<char>(prior_max);
+  int tile0 = 0;
+  for (int i = 0; i < n; ++i) {
+    char* arena = cv.take<char>(krylov_image_bytes(im[i].H, im[i].W));
+    pl.imgs.push_back(krylov_carve(arena, im[i].H, im[i].W, tile0));
+    tile0 += pl.imgs.back().ntiles;
+    const bool need_t = !im[i].t && !im[i].t_out;
+    const bool need_A = !im[i].A && !im[i].A_out;
+    pl.t_int.push_back(need_t ? cv.take<float>(static_cast<size_t>(im[i].H) * im[i].W) : nullptr);
+    pl.A_int.push_back(need_A ? cv.take<float>(4) : nullptr);
+  }
+  pl.ntiles = tile0;
+  pl.d_imgs = cv.take<KImg>(n);
+  pl.d_scal = cv.take<KScal>(n);
+  pl.d_tile_img = cv.take<int>(tile0);
+  pl.d_part = cv.take<double>(static_cast<size_t>(kKPart) * tile0);
+  pl.bytes = cv.used();
+  return pl;
+}
+
+// Front end of one batch image: t and A as given, or estimated (Section II-D);
+// lambda and Phi go straight into the image's solver planes.
+int batch_front_end(const BatchPlan& pl, int i, const dehaze_image& m, int dtype, int layout,
+                    const dehaze_params& p, const float** A_used, hipStream_t s) {
+  PriorBufs pb{};
+  carve_prior(pl.prior_ws, m.H, m.W, &pb);
+  const KImg& K = pl.imgs[i];
+  int rc;
+  const float* A = m.A;
+  float* t_dst = nullptr;
+  if (!m.t || !m.A) {
+    if ((rc = launch_patch_min(m.I, dtype, layout, m.H, m.W, m.pitch, p.patch, pb, nullptr, nullptr, s)))
+      return rc;
+    if (!m.A) {
+      float* A_dst = m.A_out ? m.A_out : pl.A_int[i];
+      if ((rc = launch_airlight(pb, m.H, m.W, p.atm_divisor, A_dst, s))) return rc;
+      A = A_dst;
+    }
+    if (!m.t) t_dst = m.t_out ? m.t_out : pl.t_int[i];
+  } else if ((rc = launch_to_planar(m.I, dtype, layout, m.H, m.W, m.pitch, pb.Ip, pb.P, s))) {
+    return rc;
+  }
+  if (m.A && m.A_out && m.A_out != m.A)
+    DZ_HIP(hipMemcpyAsync(m.A_out, m.A, 3 * sizeof(float), hipMemcpyDeviceToDevice, s));
+  FusedOut fo{nullptr, t_dst, const_cast<float*>(K.lam), const_cast<float*>(K.phi), K.P, m.W};
+  if ((rc = launch_prior_fused(m.t ? nullptr : pb.m, pb.Ip, pb.P, m.t, m.W, A, m.H, m.W, p, fo, s))) return rc;
+  *A_used = A;
+  return DEHAZE_OK;
+}
+
 }  // namespace
 
 size_t solver_workspace_bytes(int H, int W, const dehaze_params& p) {
@@ -208,12 +380,55 @@ size_t solver_workspace_bytes(int H, int W, const dehaze_params& p) {
 }
 
 int solve_one(Ctx& ctx, const SolveArgs& a, const dehaze_params& p, dehaze_stats* st, hipStream_t s) {
-  (void)ctx;
   if (p.warm_start) { set_error("warm start needs loaded network weights"); return DEHAZE_EINVAL; }
-  if (p.scheme == DEHAZE_PICARD_KRYLOV) return run_krylov(a, p, st, s);
+  if (p.scheme == DEHAZE_PICARD_KRYLOV) return run_krylov(ctx, a, p, st, s);
   return run_sweeps(a, p, st, s);
 }
 
-void solver_release(Ctx& ctx) { (void)ctx; }
+size_t batch_workspace_bytes(int n, const dehaze_image* imgs) { return plan_batch(nullptr, n, imgs).bytes; }
+
+int solve_batch(Ctx& ctx, int n, const dehaze_image* im, int dtype, int layout, const dehaze_params& p, void* ws,
+                dehaze_stats* st, hipStream_t s) {
+  if (p.warm_start) { set_error("warm start needs loaded network weights"); return DEHAZE_EINVAL; }
+  BatchPlan pl = plan_batch(ws, n, im);
+  std::vector<const float*> A_used(n, nullptr), u0(n, nullptr);
+  int rc;
+  for (int i = 0; i < n; ++i) {
+    if ((rc = batch_front_end(pl, i, im[i], dtype, layout, p, &A_used[i], s))) return rc;
+    u0[i] = im[i].u0;
+  }
+  KrylovBatch b{pl.d_imgs, pl.d_scal, pl.d_tile_img, pl.d_part, n, pl.ntiles};
+  if ((rc = krylov_init(b, pl.imgs.data(), u0.data(), s))) return rc;
+  std::vector<KScal> hs(n);
+  if ((rc = krylov_loop(ctx, b, p, hs.data(), st != nullptr, s))) return rc;
+  for (int i = 0; i < n; ++i)
+    if ((rc = krylov_output(pl.imgs[i], im[i].u, s))) return rc;
+  if (!st && p.rel_tol <= 0.0) return DEHAZE_OK;
+  int worst = DEHAZE_OK;
+  std::vector<float> Ah(3 * static_cast<size_t>(n));
+  for (int i = 0; i < n; ++i)
+    DZ_HIP(hipMemcpyAsync(&Ah[3 * i], A_used[i], 3 * sizeof(float), hipMemcpyDeviceToHost, s));
+  DZ_HIP(hipStreamSynchronize(s));
+  for (int i = 0; i < n; ++i) {
+    const int status = image_status(hs[i], p);
+    if (status == DEHAZE_ENONFINITE || (status == DEHAZE_ENOTCONV && worst == DEHAZE_OK)) worst = status;
+    if (st) {
+      fill_stats(hs[i], &st[i]);
+      st[i].status = status;
+      for (int c = 0; c < 3; ++c) st[i].A[c] = Ah[3 * i + c];
+    }
+  }
+  if (worst == DEHAZE_ENONFINITE) set_error("a residual is not finite");
+  else if (worst == DEHAZE_ENOTCONV) set_error("rel_tol %g not reached for every image", p.rel_tol);
+  return worst;
+}
+
+void solver_release(Ctx& ctx) {
+  if (!ctx.graphs) return;
+  if (ctx.graphs->exec) (void)hipGraphExecDestroy(ctx.graphs->exec);
+  if (ctx.graphs->cap) (void)hipStreamDestroy(ctx.graphs->cap);
+  delete ctx.graphs;
+  ctx.graphs = nullptr;
+}
 
 }  // namespace dz
