@@ -84,7 +84,8 @@ typedef struct dehaze_params {
   int32_t max_inner;        /* BiCGSTAB iterations per lagged-diffusivity step */
   int32_t check_every;      /* residual test every this many outer steps (>= 1) */
   int32_t atm_divisor;      /* A from the top max(1, HW / atm_divisor) dark-channel pixels */
-  int32_t warm_start;       /* 1: start from the network's prediction (needs loaded weights) */
+  int32_t warm_start;       /* 1: start the lagged-diffusivity solve from the network's prediction
+                               (needs loaded weights; u0 must then be NULL) */
   int32_t nonlocal_term;    /* 0: drop lambda G (ablation) */
   int32_t adaptive;         /* 0: lambda = lambda0 everywhere (ablation) */
   int32_t edge_preserving;  /* 0: D = 1 (ablation; the solve becomes linear) */
@@ -200,6 +201,39 @@ typedef struct dehaze_image {
 size_t dehaze_batch_workspace_size(int n, const dehaze_image* imgs, const dehaze_params* p);
 int dehaze_batch(dehaze_ctx* ctx, int n, const dehaze_image* imgs, int dtype, int layout,
                  const dehaze_params* p, void* ws, size_t ws_bytes, dehaze_stats* stats, void* stream);
+
+/* ------------------------------------------------------------ warm-start network
+ * The paper ends its introduction by pointing at hybrids of the PDE with
+ * learned models; this network supplies the starting iterate of the
+ * lagged-diffusivity solve (warm_start = 1), which then runs to its own
+ * residual test exactly as from a cold start.  Architecture: six 3x3
+ * convolutions 7 -> 32 -> 32 -> 32 -> 32 -> 32 -> 3, ReLU after the first
+ * five, zero padding, input [I^R, I^G, I^B, t, A^R, A^G, A^B] per pixel,
+ * output u / 8 (the prediction is multiplied by 8).  bfloat16 weights and
+ * activations, float32 accumulation on the matrix cores.
+ *
+ * Parameters are float32 on the host, layer by layer: W[co][ci][3][3] then
+ * b[co] (dehaze_cnn_param_count() values in all).  The context keeps a
+ * float32 master copy, the Adam moments and the bfloat16 packings.
+ * Training images are dense and share one size: I is n x 3 x H x W planar
+ * float, t n x H x W, A n x 3, target (converged solutions) n x 3 x H x W,
+ * all on the device.  The loss is the mean squared error of u against target.
+ * Errors: EINVAL (no weights loaded, wrong count, bad sizes), ENOMEM, EHIP. */
+size_t dehaze_cnn_param_count(void);
+int dehaze_cnn_set_weights(dehaze_ctx* ctx, const float* w, size_t count);   /* host; resets Adam */
+int dehaze_cnn_get_weights(dehaze_ctx* ctx, float* w, size_t count);         /* host */
+size_t dehaze_cnn_workspace_size(int n, int H, int W, int training);
+/* u (n x 3 x H x W planar) = the network's prediction. */
+int dehaze_cnn_forward(dehaze_ctx* ctx, int n, int H, int W, const float* I, const float* t, const float* A,
+                       float* u, void* ws, size_t ws_bytes, void* stream);
+/* Gradient of the loss wrt the parameters (device, param_count floats, layout
+   as above) and the loss itself (host, synchronises). */
+int dehaze_cnn_grad(dehaze_ctx* ctx, int n, int H, int W, const float* I, const float* t, const float* A,
+                    const float* target, float* grad, double* loss, void* ws, size_t ws_bytes, void* stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) with learning rate lr;
+   loss (host, nullable) receives the loss before the step. */
+int dehaze_cnn_train_step(dehaze_ctx* ctx, int n, int H, int W, const float* I, const float* t, const float* A,
+                          const float* target, float lr, double* loss, void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------ residual
  * rho = ||Phi - L_{D(u)} u||_2 / ||Phi||_2 over all channels, for planar

@@ -17,6 +17,29 @@ from __future__ import annotations
 import numpy as np
 
 LAYERS = ((7, 32), (32, 32), (32, 32), (32, 32), (32, 32), (32, 3))
+# The network predicts u / OUT_SCALE; the warm start is OUT_SCALE times its output.
+OUT_SCALE = 8.0
+
+
+def param_count() -> int:
+    return sum(co * ci * 9 + co for ci, co in LAYERS)
+
+
+def unflatten(vec):
+    """Flat parameter vector (per layer W[co][ci][3][3] then b[co]) -> [(W, b), ...]."""
+    vec = np.asarray(vec, dtype=np.float64)
+    out, off = [], 0
+    for ci, co in LAYERS:
+        W = vec[off:off + co * ci * 9].reshape(co, ci, 3, 3)
+        off += co * ci * 9
+        b = vec[off:off + co]
+        off += co
+        out.append((W, b))
+    return out
+
+
+def flatten(params) -> np.ndarray:
+    return np.concatenate([np.concatenate([W.reshape(-1), b.reshape(-1)]) for W, b in params])
 
 
 def round_bf16(x: np.ndarray) -> np.ndarray:
@@ -118,3 +141,18 @@ def adam_step(param, grad, m, v, step: int, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8)
     mhat = m / (1.0 - b1 ** step)
     vhat = v / (1.0 - b2 ** step)
     return param - lr * mhat / (np.sqrt(vhat) + eps), m, v
+
+
+def warm_start(I, t, A, params, bf16: bool = True):
+    """Starting iterate OUT_SCALE * net(features) for one image, (3, H, W).
+
+    With bf16 the input, the weights and every hidden activation are rounded
+    to bfloat16 as the GPU stores them (biases and the output stay wide).
+    """
+    x = features(I, t, A)[None]
+    if bf16:
+        params = [(round_bf16(W), b) for W, b in params]
+        y, _ = forward(x, params, act_round=round_bf16)
+    else:
+        y, _ = forward(x, params)
+    return OUT_SCALE * y[0]

@@ -95,6 +95,16 @@ _SIGS = {
                              c_void_p, c_void_p, c_void_p, c_size_t, _S, c_void_p]),
     "dehaze_batch_workspace_size": (c_size_t, [c_int, POINTER(Image), _P]),
     "dehaze_batch": (c_int, [c_void_p, c_int, POINTER(Image), c_int, c_int, _P, c_void_p, c_size_t, _S, c_void_p]),
+    "dehaze_cnn_param_count": (c_size_t, []),
+    "dehaze_cnn_set_weights": (c_int, [c_void_p, c_void_p, c_size_t]),
+    "dehaze_cnn_get_weights": (c_int, [c_void_p, c_void_p, c_size_t]),
+    "dehaze_cnn_workspace_size": (c_size_t, [c_int, c_int, c_int, c_int]),
+    "dehaze_cnn_forward": (c_int, [c_void_p, c_int, c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                   c_size_t, c_void_p]),
+    "dehaze_cnn_grad": (c_int, [c_void_p, c_int, c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                POINTER(c_double), c_void_p, c_size_t, c_void_p]),
+    "dehaze_cnn_train_step": (c_int, [c_void_p, c_int, c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p,
+                                      ctypes.c_float, POINTER(c_double), c_void_p, c_size_t, c_void_p]),
     "dehaze_residual_workspace_size": (c_size_t, [c_int, c_int, _P]),
     "dehaze_residual": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, _P, c_void_p,
                                 POINTER(c_double), c_void_p, c_size_t, c_void_p]),
@@ -292,3 +302,68 @@ def batch_workspace_bytes(shapes, params: Params = None) -> int:
     for i, (H, W) in enumerate(shapes):
         arr[i] = Image(1, H, W, W, 0, 1, None, None, None, None, None)
     return int(_lib.dehaze_batch_workspace_size(n, arr, ctypes.byref(p)))
+
+
+# ---------------------------------------------------------------- network
+def dehaze_cnn_param_count() -> int:
+    return int(_lib.dehaze_cnn_param_count())
+
+
+def dehaze_cnn_set_weights(ctx: Context, w) -> None:
+    import numpy as np
+    w = np.ascontiguousarray(w, dtype=np.float32)
+    _check(_lib.dehaze_cnn_set_weights(ctx.handle, w.ctypes.data, w.size))
+
+
+def dehaze_cnn_get_weights(ctx: Context):
+    import numpy as np
+    w = np.empty(dehaze_cnn_param_count(), dtype=np.float32)
+    _check(_lib.dehaze_cnn_get_weights(ctx.handle, w.ctypes.data, w.size))
+    return w
+
+
+def _cnn_args(I, t, A):
+    n, c, H, W = I.shape
+    for x, shape in ((I, (n, 3, H, W)), (t, (n, H, W)), (A, (n, 3))):
+        if tuple(x.shape) != shape or not x.is_contiguous() or x.dtype != torch.float32 or not x.is_cuda:
+            raise ValueError(f"expected a contiguous float32 device tensor of shape {shape}")
+    return n, H, W
+
+
+def cnn_workspace(n, H, W, training: bool, device="cuda") -> torch.Tensor:
+    return _workspace(_lib.dehaze_cnn_workspace_size(n, H, W, 1 if training else 0), device)
+
+
+def dehaze_cnn_forward(ctx: Context, I, t, A, ws=None):
+    n, H, W = _cnn_args(I, t, A)
+    u = torch.empty((n, 3, H, W), dtype=torch.float32, device=I.device)
+    need = _lib.dehaze_cnn_workspace_size(n, H, W, 0)
+    if ws is None or ws.numel() < need:
+        ws = _workspace(need, I.device)
+    _check(_lib.dehaze_cnn_forward(ctx.handle, n, H, W, I.data_ptr(), t.data_ptr(), A.data_ptr(), u.data_ptr(),
+                                   ws.data_ptr(), ws.numel(), _stream()))
+    return u
+
+
+def dehaze_cnn_grad(ctx: Context, I, t, A, target, ws=None):
+    n, H, W = _cnn_args(I, t, A)
+    g = torch.empty(dehaze_cnn_param_count(), dtype=torch.float32, device=I.device)
+    need = _lib.dehaze_cnn_workspace_size(n, H, W, 1)
+    if ws is None or ws.numel() < need:
+        ws = _workspace(need, I.device)
+    loss = c_double()
+    _check(_lib.dehaze_cnn_grad(ctx.handle, n, H, W, I.data_ptr(), t.data_ptr(), A.data_ptr(), target.data_ptr(),
+                                g.data_ptr(), ctypes.byref(loss), ws.data_ptr(), ws.numel(), _stream()))
+    return g, loss.value
+
+
+def dehaze_cnn_train_step(ctx: Context, I, t, A, target, lr: float, ws=None, want_loss: bool = True):
+    n, H, W = _cnn_args(I, t, A)
+    need = _lib.dehaze_cnn_workspace_size(n, H, W, 1)
+    if ws is None or ws.numel() < need:
+        ws = _workspace(need, I.device)
+    loss = c_double()
+    _check(_lib.dehaze_cnn_train_step(ctx.handle, n, H, W, I.data_ptr(), t.data_ptr(), A.data_ptr(),
+                                      target.data_ptr(), float(lr), ctypes.byref(loss) if want_loss else None,
+                                      ws.data_ptr(), ws.numel(), _stream()))
+    return loss.value if want_loss else None

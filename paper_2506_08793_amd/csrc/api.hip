@@ -8,6 +8,7 @@
 #include <new>
 #include <vector>
 
+#include "cnn.hpp"
 #include "internal.hpp"
 #include "solver.hpp"
 
@@ -149,7 +150,10 @@ int dehaze_ctx_create(dehaze_ctx** out, int device) {
 
 void dehaze_ctx_destroy(dehaze_ctx* ctx) {
   if (!ctx) return;
+  (void)hipSetDevice(ctx->c.device);
   solver_release(ctx->c);
+  cnn_release(ctx->c.cnn);
+  ctx->c.cnn = nullptr;
   delete ctx;
 }
 
@@ -223,9 +227,8 @@ static int check_batch(int n, const dehaze_image* imgs) {
 }
 
 size_t dehaze_batch_workspace_size(int n, const dehaze_image* imgs, const dehaze_params* p) {
-  (void)p;
-  if (check_batch(n, imgs)) return 0;
-  return batch_workspace_bytes(n, imgs);
+  if (!p || check_batch(n, imgs)) return 0;
+  return batch_workspace_bytes(n, imgs, *p);
 }
 
 int dehaze_batch(dehaze_ctx* ctx, int n, const dehaze_image* imgs, int dtype, int layout, const dehaze_params* p,
@@ -238,13 +241,79 @@ int dehaze_batch(dehaze_ctx* ctx, int n, const dehaze_image* imgs, int dtype, in
   if (dtype != DEHAZE_U8 && dtype != DEHAZE_F32) { set_error("unknown dtype %d", dtype); return DEHAZE_EINVAL; }
   if (layout != DEHAZE_HWC && layout != DEHAZE_CHW) { set_error("unknown layout %d", layout); return DEHAZE_EINVAL; }
   if (p->scheme != DEHAZE_PICARD_KRYLOV) { set_error("the batch solve runs DEHAZE_PICARD_KRYLOV only"); return DEHAZE_EINVAL; }
-  const size_t need = batch_workspace_bytes(n, imgs);
+  const size_t need = batch_workspace_bytes(n, imgs, *p);
   if (!ws || ws_bytes < need) {
     set_error("batch workspace needs %zu bytes, got %zu", need, ws_bytes);
     return DEHAZE_ENOMEM;
   }
   DZ_HIP(hipSetDevice(ctx->c.device));
   return solve_batch(ctx->c, n, imgs, dtype, layout, *p, ws, stats, static_cast<hipStream_t>(stream));
+}
+
+size_t dehaze_cnn_param_count(void) { return cnn_param_count(); }
+
+int dehaze_cnn_set_weights(dehaze_ctx* ctx, const float* w, size_t count) {
+  clear_error();
+  if (!ctx || !w) { set_error("ctx and weights are required"); return DEHAZE_EINVAL; }
+  DZ_HIP(hipSetDevice(ctx->c.device));
+  return cnn_set_weights(ctx->c, w, count, nullptr);
+}
+
+int dehaze_cnn_get_weights(dehaze_ctx* ctx, float* w, size_t count) {
+  clear_error();
+  if (!ctx || !w) { set_error("ctx and output are required"); return DEHAZE_EINVAL; }
+  DZ_HIP(hipSetDevice(ctx->c.device));
+  return cnn_get_weights(ctx->c, w, count, nullptr);
+}
+
+size_t dehaze_cnn_workspace_size(int n, int H, int W, int training) {
+  if (n < 1 || H < 1 || W < 1) return 0;
+  return training ? cnn_train_bytes(n, H, W) : cnn_forward_bytes(n, H, W);
+}
+
+static int check_cnn_call(dehaze_ctx* ctx, int n, int H, int W, const void* I, const void* t, const void* A,
+                          size_t ws_bytes, size_t need, const void* ws) {
+  if (!ctx) { set_error("ctx is NULL"); return DEHAZE_EINVAL; }
+  if (n < 1 || H < 1 || W < 1 || static_cast<long long>(n) * H * W > (1LL << 31)) {
+    set_error("bad network batch %d x %d x %d", n, H, W);
+    return DEHAZE_EINVAL;
+  }
+  if (!I || !t || !A) { set_error("I, t and A are required"); return DEHAZE_EINVAL; }
+  if (!cnn_ready(ctx->c)) { set_error("no network weights loaded"); return DEHAZE_EINVAL; }
+  if (!ws || ws_bytes < need) { set_error("network workspace needs %zu bytes, got %zu", need, ws_bytes); return DEHAZE_ENOMEM; }
+  return DEHAZE_OK;
+}
+
+int dehaze_cnn_forward(dehaze_ctx* ctx, int n, int H, int W, const float* I, const float* t, const float* A, float* u,
+                       void* ws, size_t ws_bytes, void* stream) {
+  clear_error();
+  int rc = check_cnn_call(ctx, n, H, W, I, t, A, ws_bytes, cnn_forward_bytes(n, H, W), ws);
+  if (rc) return rc;
+  if (!u) { set_error("u is required"); return DEHAZE_EINVAL; }
+  DZ_HIP(hipSetDevice(ctx->c.device));
+  const size_t plane = static_cast<size_t>(H) * W;
+  return cnn_forward(ctx->c, n, H, W, I, W, plane, 3 * plane, t, W, plane, A, u, W, 3 * plane, ws,
+                     static_cast<hipStream_t>(stream));
+}
+
+int dehaze_cnn_grad(dehaze_ctx* ctx, int n, int H, int W, const float* I, const float* t, const float* A,
+                    const float* target, float* grad, double* loss, void* ws, size_t ws_bytes, void* stream) {
+  clear_error();
+  int rc = check_cnn_call(ctx, n, H, W, I, t, A, ws_bytes, cnn_train_bytes(n, H, W), ws);
+  if (rc) return rc;
+  if (!target) { set_error("target is required"); return DEHAZE_EINVAL; }
+  DZ_HIP(hipSetDevice(ctx->c.device));
+  return cnn_grad(ctx->c, n, H, W, I, t, A, target, grad, loss, ws, static_cast<hipStream_t>(stream));
+}
+
+int dehaze_cnn_train_step(dehaze_ctx* ctx, int n, int H, int W, const float* I, const float* t, const float* A,
+                          const float* target, float lr, double* loss, void* ws, size_t ws_bytes, void* stream) {
+  clear_error();
+  int rc = check_cnn_call(ctx, n, H, W, I, t, A, ws_bytes, cnn_train_bytes(n, H, W), ws);
+  if (rc) return rc;
+  if (!target || !(lr > 0.0f)) { set_error("target and lr > 0 are required"); return DEHAZE_EINVAL; }
+  DZ_HIP(hipSetDevice(ctx->c.device));
+  return cnn_train_step(ctx->c, n, H, W, I, t, A, target, lr, loss, ws, static_cast<hipStream_t>(stream));
 }
 
 size_t dehaze_residual_workspace_size(int H, int W, const dehaze_params* p) {

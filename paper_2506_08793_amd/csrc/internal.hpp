@@ -56,11 +56,13 @@ struct Carver {
 
 // ---------------------------------------------------------------- context
 struct GraphCache;  // captured outer-step graphs (solver.hip)
+struct CnnState;    // warm-start network weights and optimiser state (cnn.hip)
 struct Ctx {
   int device = 0;
   int num_cus = 256;
   int lds_bytes = 65536;
   GraphCache* graphs = nullptr;
+  CnnState* cnn = nullptr;
 };
 
 // ---------------------------------------------------------------- launchers

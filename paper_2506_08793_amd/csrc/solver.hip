@@ -6,6 +6,7 @@
 #include <cstring>
 #include <vector>
 
+#include "cnn.hpp"
 #include "internal.hpp"
 #include "krylov.hpp"
 #include "solver.hpp"
@@ -124,10 +125,12 @@ struct KrylovPlan {
   KScal* d_scal = nullptr;
   int* d_tile_img = nullptr;
   double* d_part = nullptr;
+  float* u0w = nullptr;   // network prediction (warm start), planar pitch W
+  char* cnn_ws = nullptr;
   size_t bytes = 0;
 };
 
-KrylovPlan plan_krylov(void* ws, int H, int W) {
+KrylovPlan plan_krylov(void* ws, int H, int W, bool warm) {
   KrylovPlan pl;
   Carver cv(ws, ~size_t(0));
   char* arena = cv.take<char>(krylov_image_bytes(H, W));
@@ -138,6 +141,10 @@ KrylovPlan plan_krylov(void* ws, int H, int W) {
   pl.d_scal = cv.take<KScal>(1);
   pl.d_tile_img = cv.take<int>(nt);
   pl.d_part = cv.take<double>(static_cast<size_t>(kKPart) * nt);
+  if (warm) {
+    pl.u0w = cv.take<float>(3 * static_cast<size_t>(H) * W);
+    pl.cnn_ws = cv.take<char>(cnn_forward_bytes(1, H, W));
+  }
   pl.bytes = cv.used();
   return pl;
 }
@@ -274,7 +281,7 @@ int image_status(const KScal& k, const dehaze_params& p) {
 
 int run_krylov(Ctx& ctx, const SolveArgs& a, const dehaze_params& p, dehaze_stats* st, hipStream_t s) {
   const int H = a.H, W = a.W;
-  KrylovPlan pl = plan_krylov(a.ws, H, W);
+  KrylovPlan pl = plan_krylov(a.ws, H, W, p.warm_start != 0);
   const int P = pl.img.P;
   int rc;
   if ((rc = launch_to_planar(a.I, a.dtype, a.layout, H, W, a.pitch, pl.Ip, P, s))) return rc;
@@ -282,6 +289,13 @@ int run_krylov(Ctx& ctx, const SolveArgs& a, const dehaze_params& p, dehaze_stat
   if ((rc = launch_prior_fused(nullptr, pl.Ip, P, a.t, W, a.A, H, W, p, fo, s))) return rc;
   KrylovBatch b{pl.d_imgs, pl.d_scal, pl.d_tile_img, pl.d_part, 1, pl.img.ntiles};
   const float* u0 = a.u0;
+  if (p.warm_start) {
+    const size_t plane = static_cast<size_t>(H) * P;
+    if ((rc = cnn_forward(ctx, 1, H, W, pl.Ip, P, plane, 3 * plane, a.t, W, static_cast<size_t>(H) * W, a.A, pl.u0w,
+                          W, 3 * static_cast<size_t>(H) * W, pl.cnn_ws, s)))
+      return rc;
+    u0 = pl.u0w;
+  }
   if ((rc = krylov_init(b, &pl.img, &u0, s))) return rc;
   KScal hs{};
   if ((rc = krylov_loop(ctx, b, p, &hs, st != nullptr, s))) return rc;
@@ -310,19 +324,23 @@ struct BatchPlan {
   KScal* d_scal = nullptr;
   int* d_tile_img = nullptr;
   double* d_part = nullptr;
+  std::vector<float*> u0w;  // network predictions (warm start)
+  char* cnn_ws = nullptr;
   int ntiles = 0;
   size_t bytes = 0;
 };
 
-BatchPlan plan_batch(void* ws, int n, const dehaze_image* im) {
+BatchPlan plan_batch(void* ws, int n, const dehaze_image* im, bool warm) {
   BatchPlan pl;
   Carver cv(ws, ~size_t(0));
-  size_t prior_max = 0;
+  size_t prior_max = 0, cnn_max = 0;
   for (int i = 0; i < n; ++i) {
     PriorBufs tmp{};
     prior_max = std::max(prior_max, carve_prior(nullptr, im[i].H, im[i].W, &tmp));
+    cnn_max = std::max(cnn_max, cnn_forward_bytes(1, im[i].H, im[i].W));
   }
   pl.prior_ws = cv.take<char>(prior_max);
+  if (warm) pl.cnn_ws = cv.take<char>(cnn_max);
   int tile0 = 0;
   for (int i = 0; i < n; ++i) {
     char* arena = cv.take<char>(krylov_image_bytes(im[i].H, im[i].W));
@@ -332,6 +350,7 @@ BatchPlan plan_batch(void* ws, int n, const dehaze_image* im) {
     const bool need_A = !im[i].A && !im[i].A_out;
     pl.t_int.push_back(need_t ? cv.take<float>(static_cast<size_t>(im[i].H) * im[i].W) : nullptr);
     pl.A_int.push_back(need_A ? cv.take<float>(4) : nullptr);
+    pl.u0w.push_back(warm ? cv.take<float>(3 * static_cast<size_t>(im[i].H) * im[i].W) : nullptr);
   }
   pl.ntiles = tile0;
   pl.d_imgs = cv.take<KImg>(n);
@@ -344,7 +363,7 @@ BatchPlan plan_batch(void* ws, int n, const dehaze_image* im) {
 
 // Front end of one batch image: t and A as given, or estimated (Section II-D);
 // lambda and Phi go straight into the image's solver planes.
-int batch_front_end(const BatchPlan& pl, int i, const dehaze_image& m, int dtype, int layout,
+int batch_front_end(Ctx& ctx, const BatchPlan& pl, int i, const dehaze_image& m, int dtype, int layout,
                     const dehaze_params& p, const float** A_used, hipStream_t s) {
   PriorBufs pb{};
   carve_prior(pl.prior_ws, m.H, m.W, &pb);
@@ -368,6 +387,14 @@ int batch_front_end(const BatchPlan& pl, int i, const dehaze_image& m, int dtype
     DZ_HIP(hipMemcpyAsync(m.A_out, m.A, 3 * sizeof(float), hipMemcpyDeviceToDevice, s));
   FusedOut fo{nullptr, t_dst, const_cast<float*>(K.lam), const_cast<float*>(K.phi), K.P, m.W};
   if ((rc = launch_prior_fused(m.t ? nullptr : pb.m, pb.Ip, pb.P, m.t, m.W, A, m.H, m.W, p, fo, s))) return rc;
+  if (p.warm_start) {
+    const size_t plane = static_cast<size_t>(m.H) * pb.P;
+    const float* t_used = m.t ? m.t : t_dst;
+    if ((rc = cnn_forward(ctx, 1, m.H, m.W, pb.Ip, pb.P, plane, 3 * plane, t_used, m.W,
+                          static_cast<size_t>(m.H) * m.W, A, pl.u0w[i], m.W, 3 * static_cast<size_t>(m.H) * m.W,
+                          pl.cnn_ws, s)))
+      return rc;
+  }
   *A_used = A;
   return DEHAZE_OK;
 }
@@ -375,27 +402,41 @@ int batch_front_end(const BatchPlan& pl, int i, const dehaze_image& m, int dtype
 }  // namespace
 
 size_t solver_workspace_bytes(int H, int W, const dehaze_params& p) {
-  if (p.scheme == DEHAZE_PICARD_KRYLOV) return plan_krylov(nullptr, H, W).bytes;
+  if (p.scheme == DEHAZE_PICARD_KRYLOV) return plan_krylov(nullptr, H, W, p.warm_start != 0).bytes;
   return plan_sweeps(nullptr, H, W).bytes;
 }
 
+static int check_warm(const Ctx& ctx, const dehaze_params& p, bool has_u0) {
+  if (!p.warm_start) return DEHAZE_OK;
+  if (!cnn_ready(ctx)) { set_error("warm start needs loaded network weights"); return DEHAZE_EINVAL; }
+  if (has_u0) { set_error("warm start and an explicit u0 exclude each other"); return DEHAZE_EINVAL; }
+  if (p.scheme != DEHAZE_PICARD_KRYLOV) { set_error("warm start applies to DEHAZE_PICARD_KRYLOV"); return DEHAZE_EINVAL; }
+  return DEHAZE_OK;
+}
+
 int solve_one(Ctx& ctx, const SolveArgs& a, const dehaze_params& p, dehaze_stats* st, hipStream_t s) {
-  if (p.warm_start) { set_error("warm start needs loaded network weights"); return DEHAZE_EINVAL; }
+  int rc = check_warm(ctx, p, a.u0 != nullptr);
+  if (rc) return rc;
   if (p.scheme == DEHAZE_PICARD_KRYLOV) return run_krylov(ctx, a, p, st, s);
   return run_sweeps(a, p, st, s);
 }
 
-size_t batch_workspace_bytes(int n, const dehaze_image* imgs) { return plan_batch(nullptr, n, imgs).bytes; }
+size_t batch_workspace_bytes(int n, const dehaze_image* imgs, const dehaze_params& p) {
+  return plan_batch(nullptr, n, imgs, p.warm_start != 0).bytes;
+}
 
 int solve_batch(Ctx& ctx, int n, const dehaze_image* im, int dtype, int layout, const dehaze_params& p, void* ws,
                 dehaze_stats* st, hipStream_t s) {
-  if (p.warm_start) { set_error("warm start needs loaded network weights"); return DEHAZE_EINVAL; }
-  BatchPlan pl = plan_batch(ws, n, im);
+  bool any_u0 = false;
+  for (int i = 0; i < n; ++i) any_u0 = any_u0 || im[i].u0;
+  int rc0 = check_warm(ctx, p, any_u0);
+  if (rc0) return rc0;
+  BatchPlan pl = plan_batch(ws, n, im, p.warm_start != 0);
   std::vector<const float*> A_used(n, nullptr), u0(n, nullptr);
   int rc;
   for (int i = 0; i < n; ++i) {
-    if ((rc = batch_front_end(pl, i, im[i], dtype, layout, p, &A_used[i], s))) return rc;
-    u0[i] = im[i].u0;
+    if ((rc = batch_front_end(ctx, pl, i, im[i], dtype, layout, p, &A_used[i], s))) return rc;
+    u0[i] = p.warm_start ? pl.u0w[i] : im[i].u0;
   }
   KrylovBatch b{pl.d_imgs, pl.d_scal, pl.d_tile_img, pl.d_part, n, pl.ntiles};
   if ((rc = krylov_init(b, pl.imgs.data(), u0.data(), s))) return rc;

@@ -147,3 +147,19 @@ def uneven_batch(n: int = 64, base_seed: int = 3000, beta_haze=(0.5, 2.5), sizes
         sizes = batch_sizes(n, base_seed)
     return [hazy_image(h, w, base_seed + k, beta_haze=beta_haze, occlusion=True)
             for k, (h, w) in enumerate(sizes)]
+
+
+# ---------------------------------------------------------------- network init
+CNN_LAYERS = ((7, 32), (32, 32), (32, 32), (32, 32), (32, 32), (32, 3))
+
+
+def cnn_init_params(seed: int = 0, gain: float = 1.0) -> np.ndarray:
+    """He-normal initial weights, zero biases, as one float32 vector laid out
+    per layer as W[co][ci][3][3] followed by b[co]."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for ci, co in CNN_LAYERS:
+        std = gain * np.sqrt(2.0 / (ci * 9))
+        parts.append(rng.normal(0.0, std, size=co * ci * 9))
+        parts.append(np.zeros(co))
+    return np.concatenate(parts).astype(np.float32)

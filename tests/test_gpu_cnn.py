@@ -1,0 +1,141 @@
+"""Warm-start network on the matrix cores vs the FP64 oracle: forward values,
+parameter gradients, the first Adam step, and the warm-started solve."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from gpu_util import ctx, dev, host, require_gpu, say
+from oracle import cnn_ref as c
+from oracle import dehaze_ref as o
+
+pytestmark = pytest.mark.gpu
+
+
+def _batch(n, H, W, seed):
+    Is, ts, As = [], [], []
+    for k in range(n):
+        img = synth.hazy_image(H, W, seed + k, beta_haze=(0.5, 2.0), occlusion=True)
+        pr = o.prior(img["I"])
+        Is.append(img["I"])
+        ts.append(pr["t"].astype(np.float32))
+        As.append(pr["A"].astype(np.float32))
+    return np.stack(Is), np.stack(ts), np.stack(As)
+
+
+def _oracle_forward(params, I, t, A):
+    return np.stack([c.warm_start(I[k], t[k], A[k], params) for k in range(I.shape[0])])
+
+
+def test_forward_matches_oracle():
+    # ragged against the 32 x 8 output tiles; bf16 storage on both sides, so
+    # the residual difference is float32 accumulation order and the rare
+    # activation that rounds to the other neighbouring bf16 value
+    require_gpu()
+    import paper_2506_08793_amd as d
+    w = synth.cnn_init_params(1)
+    d.dehaze_cnn_set_weights(ctx(), w)
+    I, t, A = _batch(2, 37, 45, 10)
+    say("cnn forward 2x37x45")
+    u = host(d.dehaze_cnn_forward(ctx(), dev(I), dev(t), dev(A)))
+    ref = _oracle_forward(c.unflatten(w), I, t, A)
+    err = np.max(np.abs(u - ref))
+    scale = np.max(np.abs(ref))
+    say(f"  max-abs {err:.3e} of max|u| {scale:.3f}; mean {np.mean(np.abs(u - ref)):.3e}")
+    assert err <= 2e-2 * scale
+    assert np.mean(np.abs(u - ref)) <= 2e-3 * scale
+    assert np.array_equal(d.dehaze_cnn_get_weights(ctx()), w)
+
+
+def test_gradients_match_oracle():
+    require_gpu()
+    import paper_2506_08793_amd as d
+    w = synth.cnn_init_params(2)
+    d.dehaze_cnn_set_weights(ctx(), w)
+    I, t, A = _batch(2, 20, 35, 20)
+    rng = np.random.default_rng(0)
+    target = (rng.uniform(0.0, 20.0, size=I.shape)).astype(np.float32)
+    say("cnn gradient 2x20x35")
+    g, loss = d.dehaze_cnn_grad(ctx(), dev(I), dev(t), dev(A), dev(target))
+    g = host(g).astype(np.float64)
+    params = [(c.round_bf16(W), b) for W, b in c.unflatten(w)]
+    x = np.stack([c.features(I[k], t[k], A[k]) for k in range(I.shape[0])])
+    z6, cache = c.forward(x, params, act_round=c.round_bf16)
+    y = c.OUT_SCALE * z6
+    loss_ref, gy = c.mse(y, target.astype(np.float64))
+    grads = c.backward(cache, params, c.OUT_SCALE * gy)
+    ref = c.flatten(grads)
+    say(f"  loss gpu {loss:.6e} oracle {loss_ref:.6e}")
+    assert abs(loss - loss_ref) <= 1e-2 * loss_ref
+    off = 0
+    for k, (ci, co) in enumerate(c.LAYERS):
+        nW = ci * co * 9
+        for name, sl in (("W", slice(off, off + nW)), ("b", slice(off + nW, off + nW + co))):
+            rel = np.linalg.norm(g[sl] - ref[sl]) / np.linalg.norm(ref[sl])
+            say(f"  layer {k} {name}: relative error {rel:.3e}")
+            # bf16 storage of the back-propagated gradient (8-bit mantissa,
+            # re-rounded at every layer) bounds the agreement to about 1e-2
+            assert rel <= 5e-2
+        off += nW + co
+
+
+def test_first_adam_step_closed_form():
+    # Adam's first step moves every parameter by lr * g / (|g| + eps'), i.e.
+    # by lr against the sign of its gradient wherever |g| >> eps
+    require_gpu()
+    import paper_2506_08793_amd as d
+    w = synth.cnn_init_params(3)
+    d.dehaze_cnn_set_weights(ctx(), w)
+    I, t, A = _batch(1, 24, 40, 30)
+    target = np.full(I.shape, 5.0, dtype=np.float32)
+    say("cnn first Adam step")
+    g, _ = d.dehaze_cnn_grad(ctx(), dev(I), dev(t), dev(A), dev(target))
+    g = host(g)
+    lr = 1e-3
+    d.dehaze_cnn_train_step(ctx(), dev(I), dev(t), dev(A), dev(target), lr)
+    w1 = d.dehaze_cnn_get_weights(ctx())
+    step = w1.astype(np.float64) - w
+    # first step in closed form: m_hat = g, sqrt(v_hat) = |g|
+    want = -lr * g.astype(np.float64) / (np.abs(g.astype(np.float64)) + 1e-8)
+    # float32 parameters: the update is rounded to the parameter's ulp
+    tol = 2.0 * np.spacing(np.abs(w).astype(np.float32)).astype(np.float64) + 1e-4 * lr
+    assert np.max(np.abs(step)) <= lr * 1.001
+    assert np.all(np.abs(step - want) <= tol)
+
+
+def test_training_reduces_loss():
+    require_gpu()
+    import paper_2506_08793_amd as d
+    d.dehaze_cnn_set_weights(ctx(), synth.cnn_init_params(4))
+    I, t, A = _batch(4, 32, 32, 40)
+    target = np.stack([o.prior(I[k])["phi"] for k in range(4)]).astype(np.float32)
+    ws = d.cnn_workspace(4, 32, 32, True)
+    say("cnn training 60 steps")
+    losses = [d.dehaze_cnn_train_step(ctx(), dev(I), dev(t), dev(A), dev(target), 3e-3, ws=ws) for _ in range(60)]
+    say(f"  loss {losses[0]:.4e} -> {losses[-1]:.4e}")
+    assert losses[-1] < 0.2 * losses[0]
+
+
+def test_warm_started_solve_starts_from_prediction():
+    require_gpu()
+    import paper_2506_08793_amd as d
+    w = synth.cnn_init_params(5)
+    d.dehaze_cnn_set_weights(ctx(), w)
+    img = synth.hazy_image(40, 52, 50, beta_haze=1.0)
+    pr = o.prior(img["I"])
+    t32, A32 = pr["t"].astype(np.float32), pr["A"].astype(np.float32)
+    u_pred = c.warm_start(img["I"], t32, A32, c.unflatten(w))
+    say("warm-started solve 40x52")
+    p0 = d.dehaze_params_default(warm_start=1, max_outer=0, rel_tol=0.0)
+    u0, st0 = d.dehaze_solve(ctx(), dev(img["I"]), dev(t32), dev(A32), params=p0)
+    assert np.max(np.abs(host(u0) - u_pred)) <= 2e-2 * np.max(np.abs(u_pred))
+    lam = o.adaptive_weight(t32.astype(np.float64))
+    phi = o.reconstruction(img["I"], t32, A32, o.DEFAULT.t0)
+    _, rho_pred = o.residual(host(u0).astype(np.float64), phi, lam)
+    assert abs(st0["rel_residual0"] - rho_pred) <= 1e-4 * rho_pred + 4e-6
+    p = d.dehaze_params_default(warm_start=1, max_outer=3000, rel_tol=1e-5, check_every=16)
+    u, st = d.dehaze_solve(ctx(), dev(img["I"]), dev(t32), dev(A32), params=p)
+    say(f"  {st}")
+    assert st["converged"] and st["rel_residual"] <= 1e-5
+    with pytest.raises(d.DehazeError):
+        d.dehaze_solve(ctx(), dev(img["I"]), dev(t32), dev(A32), params=p, u0=dev(phi.astype(np.float32)))
