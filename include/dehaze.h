@@ -109,8 +109,8 @@ typedef struct dehaze_stats {
 typedef struct dehaze_ctx dehaze_ctx;
 
 /* Fills *p with the defaults listed above (scheme = DEHAZE_PICARD_KRYLOV,
-   max_outer = 5000, max_inner = 8, rel_tol = 1e-5, inner_rtol = 0.1,
-   check_every = 8).  Returns DEHAZE_EINVAL for NULL. */
+   max_outer = 5000, max_inner = 30, rel_tol = 1e-5, inner_rtol = 0.1,
+   check_every = 16, inner_refine = 0).  Returns DEHAZE_EINVAL for NULL. */
 int dehaze_params_default(dehaze_params* p);
 
 /* sizeof(dehaze_params) and sizeof(dehaze_stats), so bindings can check their mirrors. */

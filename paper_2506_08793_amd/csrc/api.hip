@@ -104,8 +104,8 @@ int dehaze_params_default(dehaze_params* p) {
   p->inner_rtol = 0.1;
   p->scheme = DEHAZE_PICARD_KRYLOV;
   p->max_outer = 5000;
-  p->max_inner = 8;
-  p->check_every = 8;
+  p->max_inner = 30;
+  p->check_every = 16;
   p->atm_divisor = 1000;
   p->warm_start = 0;
   p->nonlocal_term = 1;
