@@ -2,9 +2,11 @@
 //
 // All kernels walk the tiles of every image in the batch (one 64 x 16 tile
 // per workgroup).  Per-image sums (norms, BiCGSTAB inner products) are formed
-// deterministically: each tile writes its partial sums, and the last tile of
-// the image to finish (an atomic counter) adds the partials in a fixed order
-// and updates the image's scalars for the next launch.
+// deterministically: each tile writes its partial sums, and a reduction
+// kernel with one workgroup per image adds them in a fixed order and updates
+// the image's scalars for the next launch.  (A last-tile-done counter would
+// need a device-scope release fence in every workgroup, which on a part with
+// one L2 per XCD writes the L2 back each time.)
 #include <cmath>
 
 #include "krylov.hpp"
@@ -112,29 +114,24 @@ __device__ __forceinline__ void block_sum(double (&v)[N]) {
     }
 }
 
-// Writes this tile's N partial sums; returns true (in every thread) in the
-// last tile of the image to finish, with the image totals in tot[] (valid in
-// thread 0).  The totals are summed over tiles in index order.
+// Writes this tile's N partial sums (block sum; thread 0 stores them).
 template <int N>
-__device__ bool finish_tile(double (&v)[N], double* part, int gtile, const KImg& I, KScal* sc,
-                            double (&tot)[N]) {
-  __shared__ int is_last;
+__device__ __forceinline__ void write_partials(double (&v)[N], double* part, int gtile) {
   block_sum<N>(v);
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0)
     for (int k = 0; k < N; ++k) part[static_cast<size_t>(gtile) * kKPart + k] = v[k];
-    __threadfence();
-    const unsigned prev = atomicAdd(&sc->counter, 1u);
-    is_last = prev == static_cast<unsigned>(I.ntiles - 1);
-  }
-  __syncthreads();
-  if (!is_last) return false;
-  __threadfence();
+}
+
+// Image totals of the tile partials, summed over tiles in index order with a
+// fixed assignment to threads and a fixed tree; valid in thread 0.  Run by
+// the per-image reduction kernels (one workgroup per image) after the kernel
+// that wrote the partials, so plain loads see them.
+template <int N>
+__device__ __forceinline__ void image_sums(const KImg& I, const double* part, double (&tot)[N]) {
   for (int k = 0; k < N; ++k) tot[k] = 0.0;
-  // fixed assignment of tiles to threads and a fixed reduction tree
   for (int q = threadIdx.x; q < I.ntiles; q += NT)
     for (int k = 0; k < N; ++k) tot[k] += part[static_cast<size_t>(I.tile0 + q) * kKPart + k];
   block_sum<N>(tot);
-  return true;
 }
 
 // ------------------------------------------------------------ init / output
@@ -282,8 +279,18 @@ __global__ __launch_bounds__(NT) void k_res(const KImg* __restrict__ imgs, KScal
     }
     __syncthreads();
   }
+  write_partials<3>(acc, part, g);
+}
+
+template <int LINEAR>
+__global__ __launch_bounds__(NT) void k_red_res(const KImg* __restrict__ imgs, KScal* scal, const double* part,
+                                                 KConst kc, int final) {
+  const int im = blockIdx.x;
+  const KImg I = imgs[im];
+  KScal* sc = scal + im;
+  if (!final && sc->converged) return;
   double tot[3];
-  if (!finish_tile<3>(acc, part, g, I, sc, tot)) return;
+  image_sums<3>(I, part, tot);
   if (threadIdx.x != 0) return;
   if (!LINEAR) {
     if (sc->inner_this > 0) {  // account for the update applied since the last pass
@@ -314,7 +321,6 @@ __global__ __launch_bounds__(NT) void k_res(const KImg* __restrict__ imgs, KScal
     sc->pass_inner = 0;
     sc->inner_done = (tot[2] > 0.0 && isfinite(tot[2])) ? 0 : 1;
   }
-  sc->counter = 0;
 }
 
 __global__ __launch_bounds__(NT) void k_snapshot(const KImg* __restrict__ imgs, const KScal* __restrict__ scal,
@@ -429,13 +435,20 @@ __global__ __launch_bounds__(NT) void k_bicg_a(const KImg* __restrict__ imgs, KS
     }
     __syncthreads();
   }
+  write_partials<1>(acc, part, g);
+}
+
+__global__ __launch_bounds__(NT) void k_red_a(const KImg* __restrict__ imgs, KScal* scal, const double* part) {
+  const int im = blockIdx.x;
+  const KImg I = imgs[im];
+  KScal* sc = scal + im;
+  if (sc->converged || sc->inner_done) return;
   double tot[1];
-  if (!finish_tile<1>(acc, part, g, I, sc, tot)) return;
+  image_sums<1>(I, part, tot);
   if (threadIdx.x != 0) return;
   const double sigma = tot[0];
   if (sigma == 0.0 || !isfinite(sigma)) sc->inner_done = 1;
   else sc->alpha = sc->rho / sigma;
-  sc->counter = 0;
 }
 
 // (b) s = r - alpha v; t = L M^-1 s; omega = (t, s) / (t, t); ||s|| test.
@@ -495,8 +508,17 @@ __global__ __launch_bounds__(NT) void k_bicg_b(const KImg* __restrict__ imgs, KS
     }
     __syncthreads();
   }
+  write_partials<3>(acc, part, g);
+}
+
+__global__ __launch_bounds__(NT) void k_red_b(const KImg* __restrict__ imgs, KScal* scal, const double* part,
+                                               KConst kc) {
+  const int im = blockIdx.x;
+  const KImg I = imgs[im];
+  KScal* sc = scal + im;
+  if (sc->converged || sc->inner_done) return;
   double tot[3];
-  if (!finish_tile<3>(acc, part, g, I, sc, tot)) return;
+  image_sums<3>(I, part, tot);
   if (threadIdx.x != 0) return;
   if (!isfinite(tot[0]) || !isfinite(tot[1]) || !isfinite(tot[2])) {
     sc->inner_done = 1;
@@ -504,7 +526,6 @@ __global__ __launch_bounds__(NT) void k_bicg_b(const KImg* __restrict__ imgs, KS
     if (tot[2] <= kc.eta * kc.eta * sc->bnorm2) sc->half_done = 1;
     sc->omega = tot[1] > 0.0 ? tot[0] / tot[1] : 0.0;
   }
-  sc->counter = 0;
 }
 
 // (c) x += alpha M^-1 p + omega M^-1 s; r = s - omega t; rho = (rhat, r); beta.
@@ -545,8 +566,18 @@ __global__ __launch_bounds__(NT) void k_bicg_c(const KImg* __restrict__ imgs, KS
       }
     }
   }
+  write_partials<2>(acc, part, g);
+}
+
+__global__ __launch_bounds__(NT) void k_red_c(const KImg* __restrict__ imgs, KScal* scal, const double* part,
+                                               KConst kc) {
+  const int im = blockIdx.x;
+  const KImg I = imgs[im];
+  KScal* sc = scal + im;
+  if (sc->converged || sc->inner_done) return;
+  const int half = sc->half_done;
   double tot[2];
-  if (!finish_tile<2>(acc, part, g, I, sc, tot)) return;
+  image_sums<2>(I, part, tot);
   if (threadIdx.x != 0) return;
   sc->inner_this += 1;
   sc->pass_inner += 1;
@@ -561,7 +592,6 @@ __global__ __launch_bounds__(NT) void k_bicg_c(const KImg* __restrict__ imgs, KS
       sc->rho = rho_new;
     }
   }
-  sc->counter = 0;
 }
 
 // u += delta where this outer step ran at least one inner iteration.
@@ -624,6 +654,8 @@ int krylov_residual(const KrylovBatch& b, const KConst& c, int final, hipStream_
   DZ_KRYLOV_DISPATCH(c.R, L_RES)
 #undef L_RES
   DZ_CHECK_LAUNCH();
+  hipLaunchKernelGGL((k_red_res<0>), dim3(b.nimg), dim3(NT), 0, s, b.d_imgs, b.d_scal, b.d_part, c, final);
+  DZ_CHECK_LAUNCH();
   return DEHAZE_OK;
 }
 
@@ -632,6 +664,8 @@ int krylov_linear_residual(const KrylovBatch& b, const KConst& c, hipStream_t s)
                                     b.d_part, c, 0)
   DZ_KRYLOV_DISPATCH(c.R, L_RES)
 #undef L_RES
+  DZ_CHECK_LAUNCH();
+  hipLaunchKernelGGL((k_red_res<1>), dim3(b.nimg), dim3(NT), 0, s, b.d_imgs, b.d_scal, b.d_part, c, 0);
   DZ_CHECK_LAUNCH();
   return DEHAZE_OK;
 }
@@ -651,12 +685,18 @@ int krylov_inner(const KrylovBatch& b, const KConst& c, int it, hipStream_t s) {
                                   b.d_part, c, first, par)
   DZ_KRYLOV_DISPATCH(c.R, L_A)
   DZ_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_red_a, dim3(b.nimg), dim3(NT), 0, s, b.d_imgs, b.d_scal, b.d_part);
+  DZ_CHECK_LAUNCH();
   DZ_KRYLOV_DISPATCH(c.R, L_B)
+  DZ_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_red_b, dim3(b.nimg), dim3(NT), 0, s, b.d_imgs, b.d_scal, b.d_part, c);
   DZ_CHECK_LAUNCH();
 #undef L_A
 #undef L_B
   hipLaunchKernelGGL(k_bicg_c, dim3(b.ntiles), dim3(NT), 0, s, b.d_imgs, b.d_scal, b.d_tile_img, b.d_part, c, first,
                      par);
+  DZ_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_red_c, dim3(b.nimg), dim3(NT), 0, s, b.d_imgs, b.d_scal, b.d_part, c);
   DZ_CHECK_LAUNCH();
   return DEHAZE_OK;
 }

@@ -53,7 +53,7 @@ struct KScal {
   int outer;               // updates applied
   long long inner_total;
   long long res_evals;
-  unsigned counter;        // last-block-done counter
+  unsigned reserved;
   int pad[2];
 };
 

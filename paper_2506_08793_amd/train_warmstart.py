@@ -2,9 +2,12 @@
 
     python -m paper_2506_08793_amd.train_warmstart --n 2048 --size 256 --steps 6000 --out <path>
 
-Images are the seeded synthetic hazy images (seeds 4000 + k, beta_haze ~
-U(0.5, 2.5), occlusion edges).  Targets are the lagged-diffusivity batch
-solve run cold to relative residual 1e-5.  Progress goes to stdout.
+Images are seeded synthetic hazy images (seeds 4000 + k, beta_haze ~
+U(0.5, 2.5), occlusion edges) of size x size pixels cut from virtual
+1920 x 1080 scenes, so their object scales match the full-HD images the
+network warm-starts (--canvas 0 draws whole size x size scenes instead).
+Targets are the lagged-diffusivity batch solve run cold to relative
+residual 1e-5.  Progress goes to stdout.
 """
 from __future__ import annotations
 
@@ -29,6 +32,7 @@ def main(argv=None) -> int:
     ap.add_argument("--seed0", type=int, default=4000)
     ap.add_argument("--init-seed", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=256)
+    ap.add_argument("--canvas", default="1080x1920", help="HxW of the virtual scene, or 0")
     ap.add_argument("--out", default=ws.default_weights_path())
     args = ap.parse_args(argv)
     import synth  # seeded input generator (repository root)
@@ -37,8 +41,12 @@ def main(argv=None) -> int:
     H = W = args.size
     t0 = time.time()
     imgs = []
+    canvas = None if args.canvas in ("0", "") else tuple(int(v) for v in args.canvas.split("x"))
     for k in range(args.n):
-        imgs.append(synth.hazy_image(H, W, args.seed0 + k, beta_haze=(0.5, 2.5), occlusion=True)["I"])
+        if canvas:
+            imgs.append(synth.hazy_window(H, W, args.seed0 + k, canvas=canvas)["I"])
+        else:
+            imgs.append(synth.hazy_image(H, W, args.seed0 + k, beta_haze=(0.5, 2.5), occlusion=True)["I"])
     print(f"generated {args.n} images {H}x{W} in {time.time() - t0:.1f} s", flush=True)
     t0 = time.time()
     data, stats = None, []
@@ -55,7 +63,7 @@ def main(argv=None) -> int:
     print(f"targets: {conv}/{len(stats)} converged to 1e-5", flush=True)
     b.dehaze_cnn_set_weights(ctx, synth.cnn_init_params(args.init_seed))
     hist = ws.train(ctx, data, args.steps, batch=args.batch, lr=args.lr, log_every=500)
-    meta = {"images": args.n, "size": [H, W], "seeds": [args.seed0, args.seed0 + args.n - 1],
+    meta = {"images": args.n, "size": [H, W], "canvas": args.canvas, "seeds": [args.seed0, args.seed0 + args.n - 1],
             "beta_haze": [0.5, 2.5], "steps": args.steps, "batch": args.batch, "lr": args.lr,
             "final_loss": hist[-1][1], "targets_converged": conv, "init_seed": args.init_seed}
     ws.save(ctx, args.out, meta)

@@ -141,6 +141,72 @@ def batch_sizes(n: int, seed: int) -> list:
     return [BATCH_SIZES[int(i)] for i in idx]
 
 
+def _window_field(rng, ch: int, cw: int, ys: np.ndarray, xs: np.ndarray, n_blobs: int = 8):
+    """The _smooth_field recipe on a virtual ch x cw canvas, evaluated at rows
+    ys and columns xs (canvas coordinates); returns (values, canvas min, max)
+    with the min and max taken on a stride-8 grid of the canvas plus the window."""
+    scale = float(max(ch, cw))
+    blobs = [(rng.uniform(0.0, 1.0) * cw, rng.uniform(0.0, 1.0) * ch, rng.uniform(0.05, 0.3) * scale,
+              rng.uniform(-1.0, 1.0)) for _ in range(n_blobs)]
+    ax, ay = rng.uniform(-1.0, 1.0), rng.uniform(-1.0, 1.0)
+
+    def ev(yv, xv):
+        f = np.zeros((yv.size, xv.size))
+        for cx, cy, width, amp in blobs:
+            f += amp * np.outer(np.exp(-((yv - cy) ** 2) / (2 * width * width)),
+                                np.exp(-((xv - cx) ** 2) / (2 * width * width)))
+        return f + ax * (xv / max(cw - 1, 1))[None, :] + ay * (yv / max(ch - 1, 1))[:, None]
+
+    win = ev(ys, xs)
+    coarse = ev(np.arange(0, ch, 8, dtype=np.float64), np.arange(0, cw, 8, dtype=np.float64))
+    return win, min(win.min(), coarse.min()), max(win.max(), coarse.max())
+
+
+def hazy_window(H: int, W: int, seed: int, canvas=(1080, 1920), beta_haze=(0.5, 2.5), occlusion: bool = True) -> dict:
+    """An H x W window of a virtual canvas-sized scene drawn with the recipe
+    of hazy_image (blob widths, ramps and occluders in canvas units), so a
+    small image carries the object scales of a large one.  The window's
+    offset is drawn uniformly; fields are min-max scaled with the canvas range
+    (estimated on a stride-8 grid).  Same keys as hazy_image."""
+    ch, cw = canvas
+    if H > ch or W > cw:
+        raise ValueError("window larger than the canvas")
+    rng = np.random.default_rng(seed)
+    beta = float(rng.uniform(*beta_haze)) if isinstance(beta_haze, (tuple, list)) else float(beta_haze)
+    oy, ox = int(rng.integers(0, ch - H + 1)), int(rng.integers(0, cw - W + 1))
+    ys = np.arange(oy, oy + H, dtype=np.float64)
+    xs = np.arange(ox, ox + W, dtype=np.float64)
+    J = []
+    for _ in range(3):
+        f, lo, hi = _window_field(rng, ch, cw, ys, xs)
+        J.append(np.clip((f - lo) / max(hi - lo, 1e-300), 0.0, 1.0))
+    J = np.stack(J)
+    f, lo, hi = _window_field(rng, ch, cw, ys, xs)
+    d = 3.0 * np.clip((f - lo) / max(hi - lo, 1e-300), 0.0, 1.0)
+    if occlusion:
+        for _ in range(int(rng.integers(3, 7))):
+            depth = rng.uniform(0.0, 3.0)
+            if rng.uniform() < 0.5:
+                y0, y1 = sorted(rng.integers(0, ch + 1, size=2))
+                x0, x1 = sorted(rng.integers(0, cw + 1, size=2))
+                m = ((ys >= y0) & (ys < y1))[:, None] & ((xs >= x0) & (xs < x1))[None, :]
+            else:
+                axis = int(rng.integers(0, 2))
+                cut = int(rng.integers(0, (ch if axis == 0 else cw) + 1))
+                upper = rng.uniform() < 0.5
+                v = ys if axis == 0 else xs
+                side = (v < cut) if upper else (v >= cut)
+                m = side[:, None] & np.ones((1, W), bool) if axis == 0 else np.ones((H, 1), bool) & side[None, :]
+            d = np.where(m, depth, d)
+    t = np.exp(-beta * d)
+    A = np.asarray(A_BASE, dtype=np.float64) + rng.uniform(-0.05, 0.05, size=3)
+    noise = rng.normal(0.0, NOISE_STD, size=(3, H, W))
+    I64 = J * t[None] + A[:, None, None] * (1.0 - t[None]) + noise
+    return {"J": J, "d": d, "t_true": t, "A_true": A, "I": I64.astype(np.float32),
+            "I_u8": np.rint(np.clip(I64, 0.0, 1.0) * 255.0).astype(np.uint8), "beta_haze": beta, "seed": int(seed),
+            "offset": (oy, ox)}
+
+
 def uneven_batch(n: int = 64, base_seed: int = 3000, beta_haze=(0.5, 2.5), sizes=None):
     """Uneven-size batch; image k uses seed base_seed + k."""
     if sizes is None:
