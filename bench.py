@@ -3,7 +3,9 @@
 
 A step is one pass of the whole path over one synthetic 1024x1024 RGB float32
 hazy image: the front end (patch minimum, dark channel, airlight, t, lambda,
-Phi) followed by 200 Jacobi-scaled fixed-point sweeps of the main PDE.  The
+Phi) followed by 200 Jacobi-scaled fixed-point sweeps of the main PDE, K of
+them pipelined per launch (K and the strip height chosen by the library's
+launch-shape tuner on the first, untimed, call).  The
 headline value is Mpixel-iterations per second: H * W * sweeps / time / 1e6,
 one pixel-iteration being one sweep over the three channels of one pixel.
 
@@ -11,7 +13,8 @@ Inputs are resident in HBM before the timed region; the timed region is
 bracketed by torch.cuda.synchronize().  The sweep kernel's average duration is
 measured with HIP events on the stream the library launches on, and its
 roofline fraction is reported against the 8 TB/s HBM peak with the
-algorithmic traffic of 40 bytes per RGB pixel (read u, Phi, lambda; write u).
+algorithmic traffic of 40 bytes per RGB pixel-sweep (read u, Phi, lambda;
+write u), i.e. 40 * H * W * K bytes per launch of K sweeps.
 
 The CPU baseline is the float64 oracle on a bounded sample of the same
 workload (front end plus a few sweeps), timed on the host.
@@ -36,15 +39,23 @@ SWEEPS = 200
 SWEEP_BYTES_PER_PIXEL = 40          # u in (12) + Phi (12) + lambda (4) + u out (12)
 HBM_PEAK_GBS = 8000.0
 
-# HBM traffic of one sweep launch from rocprofv3 FETCH_SIZE / WRITE_SIZE
-# counters, scaled by a plain-copy calibration, keyed by the hash of the
-# kernel source the counters were taken on.  A different hash reports null.
-# FETCH_SIZE reads 65,544 KiB and WRITE_SIZE 131,072 KiB for a 128 MiB device
-# copy dispatch, so reads are scaled by 2.0 and writes by 1.0.
-TRAFFIC = {
-    "c3caebc264567a6b": {"bytes": (20131.0 * 2.0 + 12288.0) * 1024, "fetch_kib": 20131.0, "write_kib": 12288.0,
-                         "fetch_scale": 2.0, "write_scale": 1.0},
+# HBM-side traffic of one sweep launch from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE (KiB per dispatch), keyed by the hash of the kernel source the
+# counters were taken on and by the launch shape "KxS" (sweeps per launch x
+# strip rows).  A 128 MiB device-copy dispatch reads 65,544 KiB on FETCH_SIZE
+# and 131,072 KiB on WRITE_SIZE, so reads are scaled by 2.0 and writes by 1.0.
+# A different source hash reports null.
+FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
+TRAFFIC_KIB = {
+    "0649ddcb7a47fd54": {"1x16": [23545.9, 12864.5], "1x32": [18153.1, 12864.0], "1x64": [15457.1, 12864.0], "1x128": [14109.1, 12864.0], "2x16": [27396.6, 12288.0], "2x32": [20445.6, 12288.0], "2x64": [16872.0, 12288.0], "2x128": [15063.8, 12288.0], "3x16": [26736.3, 12928.0], "3x32": [22281.8, 12928.0], "3x64": [18565.0, 12928.0], "3x128": [16218.4, 12928.0], "4x16": [45496.5, 12288.0], "4x32": [22730.8, 12288.0], "4x64": [20508.1, 12288.0], "4x128": [17841.1, 12288.0]},
 }
+
+
+def traffic_bytes(khash: str, k: int, rows: int):
+    kib = TRAFFIC_KIB.get(khash, {}).get(f"{k}x{rows}")
+    if kib is None:
+        return None
+    return round((kib[0] * FETCH_SCALE + kib[1] * WRITE_SCALE) * 1024)
 
 
 def kernel_source_hash() -> str:
@@ -170,6 +181,8 @@ def main() -> int:
     solve_ms = float(np.mean([a.elapsed_time(b) for a, b in events]))
     sweep_s = solve_ms / 1e3 / SWEEPS
     achieved = SWEEP_BYTES_PER_PIXEL * H * W / sweep_s / 1e9
+    k_launch, strip_rows = d.dehaze_sweep_shape(ctx, H, W, d.JACOBI)
+    k_launch = max(k_launch, 1)
 
     ms_per_step = elapsed / args.steps * 1e3
     value = H * W * SWEEPS * args.steps / elapsed / 1e6
@@ -187,10 +200,10 @@ def main() -> int:
                    "eps": 1e-3},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": TRAFFIC[khash]["bytes"] if khash in TRAFFIC else None,
-                     "traffic_counters": TRAFFIC.get(khash),
-                     "kernel": "k_sweep (Jacobi)", "kernel_avg_us": round(sweep_s * 1e6, 3),
-                     "bytes_per_launch": SWEEP_BYTES_PER_PIXEL * H * W, "kernel_source": khash},
+                     "traffic": traffic_bytes(khash, k_launch, strip_rows),
+                     "kernel": "k_sweep_strip (Jacobi)", "sweeps_per_launch": k_launch, "strip_rows": strip_rows,
+                     "kernel_avg_us": round(sweep_s * k_launch * 1e6, 3),
+                     "bytes_per_launch": SWEEP_BYTES_PER_PIXEL * H * W * k_launch, "kernel_source": khash},
         "final_rel_residual": st["rel_residual"],
     }
     if args.calibrate_copy:

@@ -89,7 +89,9 @@ typedef struct dehaze_params {
   int32_t nonlocal_term;    /* 0: drop lambda G (ablation) */
   int32_t adaptive;         /* 0: lambda = lambda0 everywhere (ablation) */
   int32_t edge_preserving;  /* 0: D = 1 (ablation; the solve becomes linear) */
-  int32_t sweeps_per_launch;/* sweeps fused per kernel launch (temporal blocking); 0 = library choice */
+  int32_t sweeps_per_launch;/* explicit/Jacobi sweeps fused per kernel launch (1..4, temporal blocking;
+                               R = 2 only); 0 = time the launch shapes on the first solve of each image
+                               size (synchronises once) and keep the fastest in the context */
   int32_t inner_refine;     /* extra defect-correction passes per lagged-diffusivity step: with D frozen
                                at u_n, re-form Phi - L_{D(u_n)} u in float64 and solve again (0 = one solve) */
   int32_t reserved[5];      /* must be zero */
@@ -234,6 +236,11 @@ int dehaze_cnn_grad(dehaze_ctx* ctx, int n, int H, int W, const float* I, const 
    loss (host, nullable) receives the loss before the step. */
 int dehaze_cnn_train_step(dehaze_ctx* ctx, int n, int H, int W, const float* I, const float* t, const float* A,
                           const float* target, float lr, double* loss, void* ws, size_t ws_bytes, void* stream);
+
+/* Launch shape the context uses for explicit/Jacobi sweeps of an H x W
+   image: *sweeps_per_launch (0 if none has been chosen yet, or if the tile
+   kernel is used because g_radius != 2) and *strip_rows. */
+int dehaze_sweep_shape(const dehaze_ctx* ctx, int H, int W, int scheme, int* sweeps_per_launch, int* strip_rows);
 
 /* ------------------------------------------------------------ residual
  * rho = ||Phi - L_{D(u)} u||_2 / ||Phi||_2 over all channels, for planar

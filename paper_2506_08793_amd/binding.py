@@ -105,6 +105,7 @@ _SIGS = {
                                 POINTER(c_double), c_void_p, c_size_t, c_void_p]),
     "dehaze_cnn_train_step": (c_int, [c_void_p, c_int, c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p,
                                       ctypes.c_float, POINTER(c_double), c_void_p, c_size_t, c_void_p]),
+    "dehaze_sweep_shape": (c_int, [c_void_p, c_int, c_int, c_int, POINTER(c_int), POINTER(c_int)]),
     "dehaze_residual_workspace_size": (c_size_t, [c_int, c_int, _P]),
     "dehaze_residual": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, _P, c_void_p,
                                 POINTER(c_double), c_void_p, c_size_t, c_void_p]),
@@ -367,3 +368,10 @@ def dehaze_cnn_train_step(ctx: Context, I, t, A, target, lr: float, ws=None, wan
                                       target.data_ptr(), float(lr), ctypes.byref(loss) if want_loss else None,
                                       ws.data_ptr(), ws.numel(), _stream()))
     return loss.value if want_loss else None
+
+
+def dehaze_sweep_shape(ctx: Context, H: int, W: int, scheme: int = JACOBI):
+    """(sweeps per launch, strip rows) the context uses for H x W sweeps (0, 0 if none yet)."""
+    k, srows = c_int(), c_int()
+    _check(_lib.dehaze_sweep_shape(ctx.handle, H, W, scheme, ctypes.byref(k), ctypes.byref(srows)))
+    return k.value, srows.value

@@ -316,6 +316,12 @@ int dehaze_cnn_train_step(dehaze_ctx* ctx, int n, int H, int W, const float* I, 
   return cnn_train_step(ctx->c, n, H, W, I, t, A, target, lr, loss, ws, static_cast<hipStream_t>(stream));
 }
 
+int dehaze_sweep_shape(const dehaze_ctx* ctx, int H, int W, int scheme, int* sweeps_per_launch, int* strip_rows) {
+  clear_error();
+  if (!ctx || !sweeps_per_launch || !strip_rows) { set_error("ctx and outputs are required"); return DEHAZE_EINVAL; }
+  return sweep_shape(ctx->c, H, W, scheme, sweeps_per_launch, strip_rows);
+}
+
 size_t dehaze_residual_workspace_size(int H, int W, const dehaze_params* p) {
   (void)p;
   if (H < 1 || W < 1) return 0;

@@ -57,12 +57,14 @@ struct Carver {
 // ---------------------------------------------------------------- context
 struct GraphCache;  // captured outer-step graphs (solver.hip)
 struct CnnState;    // warm-start network weights and optimiser state (cnn.hip)
+struct SweepTune;   // autotuned sweep launch shapes per image size (solver.hip)
 struct Ctx {
   int device = 0;
   int num_cus = 256;
   int lds_bytes = 65536;
   GraphCache* graphs = nullptr;
   CnnState* cnn = nullptr;
+  SweepTune* tune = nullptr;
 };
 
 // ---------------------------------------------------------------- launchers
@@ -124,6 +126,11 @@ enum SweepMode { kExplicit = 0, kJacobi = 1, kResidual = 2 };
 int sweep_num_blocks(int H, int W);
 int launch_sweep(int mode, const float* uin, float* uout, const float* phi, const float* lam,
                  int H, int W, int P, const OpConst& c, double* partials, hipStream_t s);
+// K (1..4) pipelined sweeps in one launch, register-resident strips of S
+// output rows (R = 2, explicit or Jacobi); uin and uout must differ.
+constexpr int kMaxSweepsPerLaunch = 4;
+int launch_sweep_strip(int mode, int K, int S, const float* uin, float* uout, const float* phi, const float* lam,
+                       int H, int W, int P, const OpConst& c, hipStream_t s);
 // Deterministic sum of `n` (a, b) double pairs into out[0..1].
 int launch_reduce_pairs(const double* partials, int n, double* out, hipStream_t s);
 

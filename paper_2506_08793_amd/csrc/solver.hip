@@ -4,6 +4,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <tuple>
 #include <vector>
 
 #include "cnn.hpp"
@@ -56,7 +58,72 @@ int residual_of(const float* u, const SweepPlan& pl, int H, int W, const OpConst
   return DEHAZE_OK;
 }
 
-int run_sweeps(const SolveArgs& a, const dehaze_params& p, dehaze_stats* st, hipStream_t s) {
+}  // namespace
+
+// Launch shape of the strip sweep kernel chosen per (H, W, mode): sweeps per
+// launch K and strip height S.  Every shape computes the same values, so the
+// choice only affects speed.
+struct SweepTune {
+  std::map<std::tuple<int, int, int>, std::pair<int, int>> best;
+};
+
+namespace {
+
+constexpr int kStripHeights[] = {16, 32, 64, 128};
+
+int pick_strip_shape(Ctx& ctx, int mode, int H, int W, int P, const float* phi, const float* lam, float* scratch,
+                     const OpConst& oc, int forced_k, hipStream_t s, int* K, int* S) {
+  *K = 0;
+  *S = 0;
+  if (oc.R != 2) return DEHAZE_OK;  // the tile kernel handles other radii
+  if (!ctx.tune) ctx.tune = new SweepTune();
+  const auto key = std::make_tuple(H, W, mode);
+  auto it = ctx.tune->best.find(key);
+  if (forced_k > 0) {
+    *K = std::min(forced_k, kMaxSweepsPerLaunch);
+    *S = it != ctx.tune->best.end() ? it->second.second : 32;
+    return DEHAZE_OK;
+  }
+  if (it != ctx.tune->best.end()) {
+    *K = it->second.first;
+    *S = it->second.second;
+    return DEHAZE_OK;
+  }
+  hipEvent_t e0, e1;
+  DZ_HIP(hipEventCreate(&e0));
+  DZ_HIP(hipEventCreate(&e1));
+  float best = 1e30f;
+  int bk = 1, bs = 32;
+  int rc = DEHAZE_OK;
+  for (int k = 1; k <= kMaxSweepsPerLaunch && rc == DEHAZE_OK; ++k) {
+    for (int sh : kStripHeights) {
+      if (sh > 2 * ((H + 15) / 16) * 16 && sh > 16) continue;
+      if ((rc = launch_sweep_strip(mode, k, sh, phi, scratch, phi, lam, H, W, P, oc, s))) break;
+      if (hipEventRecord(e0, s) != hipSuccess) { rc = DEHAZE_EHIP; break; }
+      for (int i = 0; i < 3 && rc == DEHAZE_OK; ++i) rc = launch_sweep_strip(mode, k, sh, phi, scratch, phi, lam, H, W, P, oc, s);
+      if (rc) break;
+      if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { rc = DEHAZE_EHIP; break; }
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = DEHAZE_EHIP; break; }
+      const float per_sweep = ms / (3.0f * k);
+      if (per_sweep < best) {
+        best = per_sweep;
+        bk = k;
+        bs = sh;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc == DEHAZE_EHIP) set_error("timing the sweep launch shapes failed");
+  if (rc) return rc;
+  ctx.tune->best[key] = {bk, bs};
+  *K = bk;
+  *S = bs;
+  return DEHAZE_OK;
+}
+
+int run_sweeps(Ctx& ctx, const SolveArgs& a, const dehaze_params& p, dehaze_stats* st, hipStream_t s) {
   const int H = a.H, W = a.W;
   SweepPlan pl = plan_sweeps(a.ws, H, W);
   int rc;
@@ -69,8 +136,23 @@ int run_sweeps(const SolveArgs& a, const dehaze_params& p, dehaze_stats* st, hip
 
   const OpConst oc = make_opconst(p);
   const int mode = p.scheme == DEHAZE_PAPER_EXPLICIT ? kExplicit : kJacobi;
+  int K = 0, S = 0;
+  if ((rc = pick_strip_shape(ctx, mode, H, W, pl.P, pl.phi, pl.lam, pl.ub, oc, p.sweeps_per_launch, s, &K, &S)))
+    return rc;
   float* cur = pl.ua;
   float* nxt = pl.ub;
+  // n sweeps from cur, ending with the result in cur
+  auto sweeps = [&](int n) -> int {
+    while (n > 0) {
+      const int k = K > 0 ? std::min(K, n) : 1;
+      const int e = K > 0 ? launch_sweep_strip(mode, k, S, cur, nxt, pl.phi, pl.lam, H, W, pl.P, oc, s)
+                          : launch_sweep(mode, cur, nxt, pl.phi, pl.lam, H, W, pl.P, oc, nullptr, s);
+      if (e) return e;
+      std::swap(cur, nxt);
+      n -= k;
+    }
+    return DEHAZE_OK;
+  };
   int done = 0;
   bool conv = false;
   double rho0 = NAN, rho = NAN;
@@ -83,18 +165,12 @@ int run_sweeps(const SolveArgs& a, const dehaze_params& p, dehaze_stats* st, hip
       if (rho <= p.rel_tol) { conv = true; break; }
       if (done >= p.max_outer) { status = DEHAZE_ENOTCONV; break; }
       const int k = std::min(p.check_every, p.max_outer - done);
-      for (int i = 0; i < k; ++i) {
-        if ((rc = launch_sweep(mode, cur, nxt, pl.phi, pl.lam, H, W, pl.P, oc, nullptr, s))) return rc;
-        std::swap(cur, nxt);
-      }
+      if ((rc = sweeps(k))) return rc;
       done += k;
     }
   } else {
     if (st && (rc = residual_of(cur, pl, H, W, oc, &rho0, s))) return rc;
-    for (int i = 0; i < p.max_outer; ++i) {
-      if ((rc = launch_sweep(mode, cur, nxt, pl.phi, pl.lam, H, W, pl.P, oc, nullptr, s))) return rc;
-      std::swap(cur, nxt);
-    }
+    if ((rc = sweeps(p.max_outer))) return rc;
     done = p.max_outer;
     if (st) {
       if ((rc = residual_of(cur, pl, H, W, oc, &rho, s))) return rc;
@@ -418,7 +494,20 @@ int solve_one(Ctx& ctx, const SolveArgs& a, const dehaze_params& p, dehaze_stats
   int rc = check_warm(ctx, p, a.u0 != nullptr);
   if (rc) return rc;
   if (p.scheme == DEHAZE_PICARD_KRYLOV) return run_krylov(ctx, a, p, st, s);
-  return run_sweeps(a, p, st, s);
+  return run_sweeps(ctx, a, p, st, s);
+}
+
+int sweep_shape(const Ctx& ctx, int H, int W, int scheme, int* K, int* S) {
+  *K = 0;
+  *S = 0;
+  if (!ctx.tune) return DEHAZE_OK;
+  const int mode = scheme == DEHAZE_PAPER_EXPLICIT ? kExplicit : kJacobi;
+  auto it = ctx.tune->best.find(std::make_tuple(H, W, mode));
+  if (it != ctx.tune->best.end()) {
+    *K = it->second.first;
+    *S = it->second.second;
+  }
+  return DEHAZE_OK;
 }
 
 size_t batch_workspace_bytes(int n, const dehaze_image* imgs, const dehaze_params& p) {
@@ -465,6 +554,8 @@ int solve_batch(Ctx& ctx, int n, const dehaze_image* im, int dtype, int layout, 
 }
 
 void solver_release(Ctx& ctx) {
+  delete ctx.tune;
+  ctx.tune = nullptr;
   if (!ctx.graphs) return;
   if (ctx.graphs->exec) (void)hipGraphExecDestroy(ctx.graphs->exec);
   if (ctx.graphs->cap) (void)hipStreamDestroy(ctx.graphs->cap);
