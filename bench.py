@@ -59,9 +59,17 @@ def traffic_bytes(khash: str, k: int, rows: int):
 
 
 def kernel_source_hash() -> str:
+    """Hash of the sweep.hip the loaded library was built from (recorded by the
+    build), else of the file on disk with a '?' (the library may be older)."""
+    rec = os.path.join(ROOT, "paper_2506_08793_amd", "libdehaze.so.sources.json")
+    if os.path.exists(rec):
+        with open(rec) as f:
+            h = json.load(f).get("sweep.hip")
+        if h:
+            return h
     path = os.path.join(ROOT, "paper_2506_08793_amd", "csrc", "sweep.hip")
     with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+        return hashlib.sha256(f.read()).hexdigest()[:16] + "?"
 
 
 def cpu_baseline(img, sweeps: int = 6) -> dict:
@@ -138,6 +146,8 @@ def main() -> int:
     ap.add_argument("--no-secondary", action="store_true", help="skip the 1080p cold/warm images/s figures")
     ap.add_argument("--secondary-images", type=int, default=4)
     ap.add_argument("--calibrate-copy", action="store_true", help="also run a 256 MiB device copy")
+    ap.add_argument("--sweeps-per-launch", type=int, default=0, help="pin K (default: the library's tuner)")
+    ap.add_argument("--strip-rows", type=int, default=0, help="pin the strip height S (default: tuned)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -152,7 +162,8 @@ def main() -> int:
     ctx = d.Context(0)
     I = torch.from_numpy(img["I"]).cuda()
     p_prior = d.dehaze_params_default()
-    p_solve = d.dehaze_params_default(scheme=d.JACOBI, max_outer=SWEEPS, rel_tol=0.0)
+    p_solve = d.dehaze_params_default(scheme=d.JACOBI, max_outer=SWEEPS, rel_tol=0.0,
+                                      sweeps_per_launch=args.sweeps_per_launch, strip_rows=args.strip_rows)
     u = torch.empty((3, H, W), dtype=torch.float32, device="cuda")
     ws = d.solve_workspace(H, W, p_solve)
     stream = torch.cuda.current_stream()
@@ -182,6 +193,9 @@ def main() -> int:
     sweep_s = solve_ms / 1e3 / SWEEPS
     achieved = SWEEP_BYTES_PER_PIXEL * H * W / sweep_s / 1e9
     k_launch, strip_rows = d.dehaze_sweep_shape(ctx, H, W, d.JACOBI)
+    if args.sweeps_per_launch > 0 or args.strip_rows > 0:
+        k_launch = args.sweeps_per_launch or k_launch or 2
+        strip_rows = args.strip_rows or strip_rows or 32
     k_launch = max(k_launch, 1)
 
     ms_per_step = elapsed / args.steps * 1e3

@@ -94,7 +94,9 @@ typedef struct dehaze_params {
                                size (synchronises once) and keep the fastest in the context */
   int32_t inner_refine;     /* extra defect-correction passes per lagged-diffusivity step: with D frozen
                                at u_n, re-form Phi - L_{D(u_n)} u in float64 and solve again (0 = one solve) */
-  int32_t reserved[5];      /* must be zero */
+  int32_t strip_rows;       /* output rows per wavefront of the register-resident sweep kernel; 0 = the
+                               tuned value (every value gives bit-identical results) */
+  int32_t reserved[4];      /* must be zero */
 } dehaze_params;
 
 typedef struct dehaze_stats {

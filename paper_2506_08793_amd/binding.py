@@ -32,7 +32,7 @@ class Params(ctypes.Structure):
         ("scheme", c_int32), ("max_outer", c_int32), ("max_inner", c_int32), ("check_every", c_int32),
         ("atm_divisor", c_int32), ("warm_start", c_int32), ("nonlocal_term", c_int32),
         ("adaptive", c_int32), ("edge_preserving", c_int32), ("sweeps_per_launch", c_int32),
-        ("inner_refine", c_int32), ("reserved", c_int32 * 5),
+        ("inner_refine", c_int32), ("strip_rows", c_int32), ("reserved", c_int32 * 4),
     ]
 
     def replace(self, **kw) -> "Params":

@@ -8,6 +8,8 @@ from __future__ import annotations
 
 import concurrent.futures
 import glob
+import hashlib
+import json
 import os
 import shutil
 import subprocess
@@ -17,11 +19,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdehaze.so")
+# sha256 (first 16 hex digits) of every source the library was built from,
+# written beside it, so a measurement can name the code it ran
+SOURCES_JSON = LIB + ".sources.json"
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 COMMON = [
-    "-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-Wall", "-Wno-unused-result",
+    "-O3", "-std=c++20", f"--offload-arch={ARCH}", "-fPIC", "-Wall", "-Wno-unused-result",
     # keep the compiler from forming packed fp32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     # correctly rounded float32 division and square root unless a kernel asks
@@ -44,6 +49,10 @@ def build(verbose: bool = False) -> str:
     """Compile every csrc/*.hip and link libdehaze.so; returns its path."""
     os.makedirs(BUILD_DIR, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+    digests = {}
+    for f in sorted(glob.glob(os.path.join(CSRC, "*"))):
+        with open(f, "rb") as fh:
+            digests[os.path.basename(f)] = hashlib.sha256(fh.read()).hexdigest()[:16]
     workers = min(len(srcs), max(1, min(8, os.cpu_count() or 1)))
     with concurrent.futures.ThreadPoolExecutor(workers) as ex:
         objs = list(ex.map(_compile, srcs))
@@ -53,6 +62,8 @@ def build(verbose: bool = False) -> str:
     if res.returncode != 0:
         raise RuntimeError(f"link failed:\n{' '.join(cmd)}\n{res.stdout}\n{res.stderr}")
     os.replace(tmp, LIB)
+    with open(SOURCES_JSON, "w") as fh:
+        json.dump(digests, fh, indent=1, sort_keys=True)
     if verbose:
         print(f"built {LIB} from {len(srcs)} sources")
     return LIB

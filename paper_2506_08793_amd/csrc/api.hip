@@ -51,6 +51,9 @@ int check_params(const dehaze_params* p) {
   if (!(p->theta > 0.0) || !std::isfinite(p->tau)) { set_error("theta must be positive"); return DEHAZE_EINVAL; }
   if (p->sweeps_per_launch < 0) { set_error("sweeps_per_launch must be >= 0"); return DEHAZE_EINVAL; }
   if (p->inner_refine < 0) { set_error("inner_refine must be >= 0"); return DEHAZE_EINVAL; }
+  if (p->strip_rows < 0) { set_error("strip_rows must be >= 0"); return DEHAZE_EINVAL; }
+  for (int r : p->reserved)
+    if (r != 0) { set_error("reserved fields of dehaze_params must be zero"); return DEHAZE_EINVAL; }
   if (!(p->inner_rtol > 0.0)) { set_error("inner_rtol must be positive"); return DEHAZE_EINVAL; }
   return DEHAZE_OK;
 }
@@ -112,6 +115,7 @@ int dehaze_params_default(dehaze_params* p) {
   p->adaptive = 1;
   p->edge_preserving = 1;
   p->sweeps_per_launch = 0;
+  p->strip_rows = 0;
   return DEHAZE_OK;
 }
 

@@ -129,6 +129,9 @@ int launch_sweep(int mode, const float* uin, float* uout, const float* phi, cons
 // K (1..4) pipelined sweeps in one launch, register-resident strips of S
 // output rows (R = 2, explicit or Jacobi); uin and uout must differ.
 constexpr int kMaxSweepsPerLaunch = 4;
+// Whether a plane of H rows of pitch P is addressable by the strip kernel
+// (byte offsets below 2^31); larger planes use the tile kernel.
+bool strip_fits(int H, int P);
 int launch_sweep_strip(int mode, int K, int S, const float* uin, float* uout, const float* phi, const float* lam,
                        int H, int W, int P, const OpConst& c, hipStream_t s);
 // Deterministic sum of `n` (a, b) double pairs into out[0..1].

@@ -69,19 +69,23 @@ struct SweepTune {
 
 namespace {
 
-constexpr int kStripHeights[] = {16, 32, 64, 128};
+constexpr int kStripHeights[] = {8, 12, 16, 20, 24, 28, 32, 40, 48, 64, 96, 128};
 
-int pick_strip_shape(Ctx& ctx, int mode, int H, int W, int P, const float* phi, const float* lam, float* scratch,
-                     const OpConst& oc, int forced_k, hipStream_t s, int* K, int* S) {
+// Times every shape on sweeps from u to scratch (the caller's starting
+// iterate and the other half of its ping-pong pair), so the trial launches
+// touch the same buffers as the solve.
+int pick_strip_shape(Ctx& ctx, int mode, int H, int W, int P, const float* u, const float* phi, const float* lam,
+                     float* scratch, const OpConst& oc, int forced_k, int forced_s, hipStream_t s, int* K, int* S) {
   *K = 0;
   *S = 0;
-  if (oc.R != 2) return DEHAZE_OK;  // the tile kernel handles other radii
+  if (oc.R != 2 || !strip_fits(H, P)) return DEHAZE_OK;  // the tile kernel handles these
   if (!ctx.tune) ctx.tune = new SweepTune();
   const auto key = std::make_tuple(H, W, mode);
   auto it = ctx.tune->best.find(key);
-  if (forced_k > 0) {
-    *K = std::min(forced_k, kMaxSweepsPerLaunch);
-    *S = it != ctx.tune->best.end() ? it->second.second : 32;
+  const bool tuned = it != ctx.tune->best.end();
+  if (forced_k > 0 || forced_s > 0) {
+    *K = forced_k > 0 ? std::min(forced_k, kMaxSweepsPerLaunch) : (tuned ? it->second.first : 2);
+    *S = forced_s > 0 ? forced_s : (tuned ? it->second.second : 32);
     return DEHAZE_OK;
   }
   if (it != ctx.tune->best.end()) {
@@ -96,11 +100,15 @@ int pick_strip_shape(Ctx& ctx, int mode, int H, int W, int P, const float* phi, 
   int bk = 1, bs = 32;
   int rc = DEHAZE_OK;
   for (int k = 1; k <= kMaxSweepsPerLaunch && rc == DEHAZE_OK; ++k) {
+    int prev_strips = -1;
     for (int sh : kStripHeights) {
-      if (sh > 2 * ((H + 15) / 16) * 16 && sh > 16) continue;
-      if ((rc = launch_sweep_strip(mode, k, sh, phi, scratch, phi, lam, H, W, P, oc, s))) break;
+      // heights that give the same strip count as the previous one add nothing
+      const int strips = (H + sh - 1) / sh;
+      if (strips == prev_strips) continue;
+      prev_strips = strips;
+      if ((rc = launch_sweep_strip(mode, k, sh, u, scratch, phi, lam, H, W, P, oc, s))) break;
       if (hipEventRecord(e0, s) != hipSuccess) { rc = DEHAZE_EHIP; break; }
-      for (int i = 0; i < 3 && rc == DEHAZE_OK; ++i) rc = launch_sweep_strip(mode, k, sh, phi, scratch, phi, lam, H, W, P, oc, s);
+      for (int i = 0; i < 3 && rc == DEHAZE_OK; ++i) rc = launch_sweep_strip(mode, k, sh, u, scratch, phi, lam, H, W, P, oc, s);
       if (rc) break;
       if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { rc = DEHAZE_EHIP; break; }
       float ms = 0.0f;
@@ -137,7 +145,8 @@ int run_sweeps(Ctx& ctx, const SolveArgs& a, const dehaze_params& p, dehaze_stat
   const OpConst oc = make_opconst(p);
   const int mode = p.scheme == DEHAZE_PAPER_EXPLICIT ? kExplicit : kJacobi;
   int K = 0, S = 0;
-  if ((rc = pick_strip_shape(ctx, mode, H, W, pl.P, pl.phi, pl.lam, pl.ub, oc, p.sweeps_per_launch, s, &K, &S)))
+  if ((rc = pick_strip_shape(ctx, mode, H, W, pl.P, pl.ua, pl.phi, pl.lam, pl.ub, oc, p.sweeps_per_launch, p.strip_rows, s,
+                             &K, &S)))
     return rc;
   float* cur = pl.ua;
   float* nxt = pl.ub;

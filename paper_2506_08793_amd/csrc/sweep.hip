@@ -17,6 +17,7 @@
 // the update.  The workload is bound by HBM traffic (40 bytes per RGB pixel:
 // read u, Phi, lambda, write u); the operator itself never touches HBM.
 #include <cmath>
+#include <utility>
 
 #include "internal.hpp"
 
@@ -248,14 +249,112 @@ __device__ __forceinline__ float from_right(float v) {
   return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x130, 0xF, 0xF, true));
 }
 
-template <int K, int MODE>
+// Buffer resource of one plane: the row offset then travels in a scalar
+// register and the lane's column offset is fixed, so no per-load address
+// arithmetic is left in the vector ALU.  Word 3 is the gfx9-family default
+// (32-bit dwords, no swizzle).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const float* base, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), 0, static_cast<int>(bytes), 0x00020000);
+}
+
+// out where the lane's bit of `live` is set, else 0 (one v_cndmask)
+__device__ __forceinline__ float keep_lanes(float out, unsigned long long live) {
+  float r;
+  asm volatile("v_cndmask_b32 %0, 0, %1, %2" : "=v"(r) : "v"(out), "s"(live));
+  return r;
+}
+
+// Register state of one sweep level: windows over the last four rows it
+// received (rows j-2 .. j+1 when it is about to produce row j), the flux and
+// coefficient of the face above row j, and its Phi / lambda prefetch rings.
+template <int PF>
+struct StripLevel {
+  float U[4], SL[4], SR[4], GH[4];
+  float qT, DT;
+  float ph[PF], la[PF];
+};
+
+struct StripConst {
+  float w0, w1, w2, eps, wc2, theta, tau;
+};
+
+// Face coefficient 1 / (|(gn, gt)| + eps) of Appendix A-2, or 1 without edge
+// preservation.
+template <bool EDGE>
+__device__ __forceinline__ float strip_face(float gn, float gt, float eps) {
+  return EDGE ? __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(__builtin_fmaf(gn, gn, gt * gt)) + eps) : 1.0f;
+}
+
+// One row step of level L: takes the level's input row v (row j + 2), shifts
+// the windows and, when ACTIVE, returns the updated value of row j.  FIRST
+// marks the level's first active row, whose top face is formed from the
+// windows instead of the previous row.
+template <int MODE, bool EDGE, bool ACTIVE, bool FIRST, int PF>
+__device__ __forceinline__ float strip_level(StripLevel<PF>& L, float v, int q, const StripConst& k) {
+#pragma clang fp contract(off)
+  const float sl1 = from_left(v), sr1 = from_right(v);
+  const float sl2 = from_left(sl1), sr2 = from_right(sr1);
+  const float ghn = __builtin_fmaf(k.w2, sl2 + sr2, __builtin_fmaf(k.w1, sl1 + sr1, k.w0 * v));
+  float out = 0.0f;
+  if (ACTIVE) {
+    const float up = L.U[1], u0 = L.U[2], dn = L.U[3];
+    if (FIRST) {
+      const float gny_t = u0 - up;
+      const float gty_t = 0.5f * (L.SR[1] - L.SL[1]);
+      L.DT = strip_face<EDGE>(gny_t, gty_t, k.eps);
+      L.qT = L.DT * gny_t;
+    }
+    const float G = __builtin_fmaf(k.w2, L.GH[0] + ghn, __builtin_fmaf(k.w1, L.GH[1] + L.GH[3], k.w0 * L.GH[2]));
+    // face right of (x, j): normal u(x+1) - u(x), tangential at this cell
+    const float gnx = L.SR[2] - u0;
+    const float gtx = 0.5f * (dn - up);
+    const float DR = strip_face<EDGE>(gnx, gtx, k.eps);
+    const float qR = DR * gnx;
+    const float DL = from_left(DR), qL = from_left(qR);
+    // face below (x, j): normal u(j+1) - u(j), tangential at this cell
+    const float gny = dn - u0;
+    const float gty = 0.5f * (L.SR[2] - L.SL[2]);
+    const float DB = strip_face<EDGE>(gny, gty, k.eps);
+    const float qB = DB * gny;
+    const float div = (qR - qL) + (qB - L.qT);
+    const float phc = L.ph[q], lac = L.la[q];
+    const float r_ = phc - __builtin_fmaf(lac, G, -div);
+    if (MODE == kExplicit) {
+      out = __builtin_fmaf(k.tau, r_, u0);
+    } else {
+      const float d = __builtin_fmaf(lac, k.wc2, (DL + DR) + (L.DT + DB));
+      out = __builtin_fmaf(k.theta * r_, __builtin_amdgcn_rcpf(d), u0);
+    }
+    L.qT = qB;
+    L.DT = DB;
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    L.U[i] = L.U[i + 1];
+    L.SL[i] = L.SL[i + 1];
+    L.SR[i] = L.SR[i + 1];
+    L.GH[i] = L.GH[i + 1];
+  }
+  L.U[3] = v;
+  L.SL[3] = sl1;
+  L.SR[3] = sr1;
+  L.GH[3] = ghn;
+  return out;
+}
+
+// Sweep level s lags level s - 1 by two rows and must produce rows
+// [y0 - 2(K-1-s), y1 - 1 + 2(K-1-s)].  The walk starts at input row
+// y0 - 2K; level s is first active at step 4 + 4s, so in head block b
+// (steps 4b .. 4b+3, b = 0..K) levels 0 .. b-1 are active, and after the
+// head every level is.  The walk ends with the last level at row y1 - 1.
+// Rows of the earlier levels beyond their range are computed and unused.
+template <int K, int MODE, bool EDGE>
 __global__ __launch_bounds__(256) void k_sweep_strip(const float* __restrict__ uin, float* __restrict__ uout,
                                                       const float* __restrict__ phi, const float* __restrict__ lam,
                                                       int H, int W, int P, int S, int ncols, int nwaves, OpConst oc) {
-  // Contraction off and every fused multiply-add spelled out: the operation
-  // sequence of an output value is then fixed, whatever K and S are.
 #pragma clang fp contract(off)
   constexpr int OW = 64 - 4 * K;
+  constexpr int PF = 4;  // rows in flight; also the unroll of the walk
   const int lane = threadIdx.x & 63;
   // the wavefront index is uniform: keep everything derived from it scalar
   const int gw = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -265,125 +364,121 @@ __global__ __launch_bounds__(256) void k_sweep_strip(const float* __restrict__ u
   const int col = rest % ncols, strip = rest / ncols;
   const int x = col * OW - 2 * K + lane;
   const bool xin = x >= 0 && x < W;
+  const unsigned long long live = __builtin_amdgcn_ballot_w64(xin);
   const int y0 = strip * S;
-  const int r0 = y0 - 2 * K - 2;
-  const int r1 = min(y0 + S, H) + 2 * K - 1;
+  const int y1 = min(y0 + S, H);
+  const int rs = y0 - 2 * K;  // first input row of the walk
   const bool out_lane = lane >= 2 * K && lane < 2 * K + OW && xin;
+  const unsigned plane_bytes = static_cast<unsigned>(H) * P * 4u;
   const size_t plane = static_cast<size_t>(H) * P;
-  const float* ui = uin + c * plane;
-  const float* ph = phi + c * plane;
-  float* uo = uout + c * plane;
-  const float w0 = oc.w[2], w1 = oc.w[1], w2 = oc.w[0];
-  const float eps = oc.eps;
-  const float wc2 = oc.wc2;
-  const bool nonlocal = oc.nonlocal_term != 0;
-  const bool edge = oc.edge_preserving != 0;
+  const __amdgpu_buffer_rsrc_t ru = plane_rsrc(uin + c * plane, plane_bytes);
+  const __amdgpu_buffer_rsrc_t rp = plane_rsrc(phi + c * plane, plane_bytes);
+  const __amdgpu_buffer_rsrc_t rl = plane_rsrc(lam, plane_bytes);
+  const __amdgpu_buffer_rsrc_t ro = plane_rsrc(uout + c * plane, plane_bytes);
+  const int voff = min(max(x, 0), W - 1) * 4;
+  StripConst k;
+  // without the nonlocal term every Gaussian weight is zero, so lambda G(u)
+  // and its diagonal vanish
+  const bool nl = oc.nonlocal_term != 0;
+  k.w0 = nl ? oc.w[2] : 0.0f;
+  k.w1 = nl ? oc.w[1] : 0.0f;
+  k.w2 = nl ? oc.w[0] : 0.0f;
+  k.wc2 = nl ? oc.wc2 : 0.0f;
+  k.eps = oc.eps;
+  k.theta = oc.theta;
+  k.tau = oc.tau;
 
-  float U[K][4], SL[K][3], SR[K][3], GH[K][5], qT[K], DT[K];
+  // Loads are unconditional from clamped rows; u of a row or column outside
+  // the image is zeroed with a bit mask (a select would be turned back into a
+  // branch around the load).  Phi and lambda need no mask: every value
+  // computed from them for a ghost cell is masked before it is used.
+  auto soff = [&](int r) { return min(max(r, 0), H - 1) * P * 4; };
+  // u of a row or column outside the image is zeroed when it is consumed
+  auto load_u = [&](int r) -> float {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(ru, voff, soff(r), 0));
+  };
+  auto load_f = [&](__amdgpu_buffer_rsrc_t rs_, int j) -> float {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs_, voff, soff(j), 0));
+  };
+
+  StripLevel<PF> lv[K];
+  float qv[PF];
 #pragma unroll
   for (int s = 0; s < K; ++s) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) U[s][i] = 0.0f;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) SL[s][i] = SR[s][i] = 0.0f;
-#pragma unroll
-    for (int i = 0; i < 5; ++i) GH[s][i] = 0.0f;
-    qT[s] = DT[s] = 0.0f;
+    for (int i = 0; i < 4; ++i) lv[s].U[i] = lv[s].SL[i] = lv[s].SR[i] = lv[s].GH[i] = 0.0f;
+    lv[s].qT = lv[s].DT = 0.0f;
   }
-  // Loads are unconditional from clamped addresses and then selected, so no
-  // branch surrounds them and the compiler can keep PF rows in flight.
-  const int xc = min(max(x, 0), W - 1);
-  auto row_ok = [&](int r) -> bool { return r >= 0 && r < H; };
-  auto addr = [&](int r) -> size_t { return static_cast<size_t>(min(max(r, 0), H - 1)) * P + xc; };
-  // invalid lanes are zeroed with a bit mask (a select would be turned back
-  // into a branch around the load)
-  const int xmask = xin ? -1 : 0;
-  auto masked = [&](float v, bool ok) -> float {
-    return __builtin_bit_cast(float, __builtin_bit_cast(int, v) & (ok ? xmask : 0));
-  };
-  auto load_u = [&](int r) -> float { return masked(ui[addr(r)], row_ok(r)); };
-  auto load_ph = [&](int j) -> float { return masked(ph[addr(j)], row_ok(j)); };
-  auto load_lam = [&](int j) -> float { return masked(lam[addr(j)], nonlocal && row_ok(j)); };
-  constexpr int PF = 4;  // rows in flight
-  // Phi and lambda are loaded once per row, for the first sweep level (row
-  // r - 2); level s uses the row of 2s steps earlier, kept in a delay line.
-  constexpr int NH = 2 * (K - 1) + 1;
-  float qv[PF], qph[PF], qla[PF];
-  float hph[NH], hla[NH];
+  // step r serves level s with Phi / lambda of row r - 2(s + 1)
 #pragma unroll
-  for (int d = 0; d < NH; ++d) hph[d] = hla[d] = 0.0f;
-#pragma unroll
-  for (int q = 0; q < PF; ++q) {
-    qv[q] = load_u(r0 + q);
-    qph[q] = load_ph(r0 + q - 2);
-    qla[q] = load_lam(r0 + q - 2);
-  }
-  // the walk is padded to a multiple of PF; the extra rows are never stored
-  const int nsteps = (r1 - r0 + 1 + PF - 1) / PF * PF;
-  for (int rb = r0; rb < r0 + nsteps; rb += PF) {
-#pragma unroll
-    for (int q = 0; q < PF; ++q) {
-    const int r = rb + q;
-    float v = qv[q];
-#pragma unroll
-    for (int d = NH - 1; d > 0; --d) {
-      hph[d] = hph[d - 1];
-      hla[d] = hla[d - 1];
-    }
-    hph[0] = qph[q];
-    hla[0] = qla[q];
-    qv[q] = load_u(r + PF);
-    qph[q] = load_ph(r + PF - 2);
-    qla[q] = load_lam(r + PF - 2);
-    float phc[K], lac[K];
+  for (int q = 0; q < PF - 1; ++q) {
+    qv[q] = load_u(rs + q);
 #pragma unroll
     for (int s = 0; s < K; ++s) {
-      phc[s] = hph[2 * s];
-      lac[s] = hla[2 * s];
+      lv[s].ph[q] = load_f(rp, rs + q - 2 * (s + 1));
+      lv[s].la[q] = load_f(rl, rs + q - 2 * (s + 1));
     }
+  }
+
+  // One row step; levels >= NACT only shift their windows.  Outputs of
+  // levels below K - 1 feed the next level and are zeroed outside the image;
+  // the last level stores rows [y0, y1) of its own lanes.
+  auto step = [&](auto nact_c, auto first_c, int r, int q) {
+    constexpr int NACT = decltype(nact_c)::value;
+    constexpr int FIRSTLV = decltype(first_c)::value;  // level whose first row this is, or -1
+    float v = keep_lanes(qv[q], (r >= 0 && r < H) ? live : 0ull);
+    qv[(q + PF - 1) % PF] = load_u(r + PF - 1);
 #pragma unroll
     for (int s = 0; s < K; ++s) {
-      // level s + 1 receives row j + 2 of level s and produces row j
       const int j = r - 2 * (s + 1);
-      const float sl1 = from_left(v), sr1 = from_right(v);
-      const float sl2 = from_left(sl1), sr2 = from_right(sr1);
-      const float ghn = __builtin_fmaf(w2, sl2 + sr2, __builtin_fmaf(w1, sl1 + sr1, w0 * v));
-      U[s][0] = U[s][1]; U[s][1] = U[s][2]; U[s][2] = U[s][3]; U[s][3] = v;
-      SL[s][0] = SL[s][1]; SL[s][1] = SL[s][2]; SL[s][2] = sl1;
-      SR[s][0] = SR[s][1]; SR[s][1] = SR[s][2]; SR[s][2] = sr1;
-      GH[s][0] = GH[s][1]; GH[s][1] = GH[s][2]; GH[s][2] = GH[s][3]; GH[s][3] = GH[s][4]; GH[s][4] = ghn;
-      const float u0 = U[s][1];
-      const float G = __builtin_fmaf(w2, GH[s][0] + GH[s][4], __builtin_fmaf(w1, GH[s][1] + GH[s][3], w0 * GH[s][2]));
-      // face right of (x, j): normal u(x+1) - u(x), tangential at this cell
-      const float gnx = SR[s][0] - u0;
-      const float gtx = 0.5f * (U[s][2] - U[s][0]);
-      const float DR =
-          edge ? __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(__builtin_fmaf(gnx, gnx, gtx * gtx)) + eps) : 1.0f;
-      const float qR = DR * gnx;
-      const float DL = from_left(DR), qL = from_left(qR);
-      // face below (x, j): normal u(j+1) - u(j), tangential at this cell
-      const float gny = U[s][2] - u0;
-      const float gty = 0.5f * (SR[s][0] - SL[s][0]);
-      const float DB =
-          edge ? __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(__builtin_fmaf(gny, gny, gty * gty)) + eps) : 1.0f;
-      const float qB = DB * gny;
-      const float div = (qR - qL) + (qB - qT[s]);
-      const float r_ = phc[s] - __builtin_fmaf(lac[s], G, -div);
       float out;
-      if (MODE == kExplicit) {
-        out = __builtin_fmaf(oc.tau, r_, u0);
+      if (s < NACT) {
+        if (s == FIRSTLV) out = strip_level<MODE, EDGE, true, true>(lv[s], v, q, k);
+        else out = strip_level<MODE, EDGE, true, false>(lv[s], v, q, k);
       } else {
-        const float d = __builtin_fmaf(lac[s], wc2, (DL + DR) + (DT[s] + DB));
-        out = __builtin_fmaf(oc.theta * r_, __builtin_amdgcn_rcpf(d), u0);
+        out = strip_level<MODE, EDGE, false, false>(lv[s], v, q, k);
       }
-      qT[s] = qB;
-      DT[s] = DB;
-      out = masked(out, j >= 0 && j < H);  // ghost cells stay zero
-      if (s == K - 1 && out_lane && j >= y0 && j < y0 + S && j < H) uo[static_cast<size_t>(j) * P + x] = out;
+      lv[s].ph[(q + PF - 1) % PF] = load_f(rp, r + PF - 1 - 2 * (s + 1));
+      lv[s].la[(q + PF - 1) % PF] = load_f(rl, r + PF - 1 - 2 * (s + 1));
+      if (s < NACT) {
+        if (s < K - 1) {
+          out = keep_lanes(out, (j >= 0 && j < H) ? live : 0ull);
+        } else if (j >= y0 && j < y1) {
+          if (out_lane) __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, out), ro, voff, j * P * 4, 0);
+        }
+      }
       v = out;
     }
-    }
+  };
+  // head: block b (0..K) has levels 0 .. b-1 active, level b-1 from its first
+  // row on
+  int r = rs;
+  [&]<int... B>(std::integer_sequence<int, B...>) {
+    (([&] {
+       constexpr int b = B;
+       step(std::integral_constant<int, b>{}, std::integral_constant<int, b - 1>{}, r, 0);
+#pragma unroll
+       for (int q = 1; q < PF; ++q) step(std::integral_constant<int, b>{}, std::integral_constant<int, -1>{}, r + q, q);
+       r += PF;
+     }()), ...);
+  }(std::make_integer_sequence<int, K + 1>{});
+  // body: every level active
+  const int rend = y1 - 1 + 2 * K;  // last step: the last level at row y1 - 1
+  for (; r <= rend; r += PF) {
+#pragma unroll
+    for (int q = 0; q < PF; ++q) step(std::integral_constant<int, K>{}, std::integral_constant<int, -1>{}, r + q, q);
   }
+}
+
+template <int K, bool EDGE>
+void launch_strip_ke(int mode, dim3 grid, const float* uin, float* uout, const float* phi, const float* lam, int H,
+                     int W, int P, int S, int ncols, int nwaves, const OpConst& c, hipStream_t s) {
+  if (mode == kExplicit)
+    hipLaunchKernelGGL((k_sweep_strip<K, kExplicit, EDGE>), grid, dim3(256), 0, s, uin, uout, phi, lam, H, W, P, S,
+                       ncols, nwaves, c);
+  else
+    hipLaunchKernelGGL((k_sweep_strip<K, kJacobi, EDGE>), grid, dim3(256), 0, s, uin, uout, phi, lam, H, W, P, S,
+                       ncols, nwaves, c);
 }
 
 template <int K>
@@ -394,12 +489,10 @@ int launch_strip_k(int mode, const float* uin, float* uout, const float* phi, co
   const int nstrips = (H + S - 1) / S;
   const int nwaves = 3 * ncols * nstrips;
   dim3 grid((nwaves + 3) / 4);
-  if (mode == kExplicit)
-    hipLaunchKernelGGL((k_sweep_strip<K, kExplicit>), grid, dim3(256), 0, s, uin, uout, phi, lam, H, W, P, S, ncols,
-                       nwaves, c);
+  if (c.edge_preserving)
+    launch_strip_ke<K, true>(mode, grid, uin, uout, phi, lam, H, W, P, S, ncols, nwaves, c, s);
   else
-    hipLaunchKernelGGL((k_sweep_strip<K, kJacobi>), grid, dim3(256), 0, s, uin, uout, phi, lam, H, W, P, S, ncols,
-                       nwaves, c);
+    launch_strip_ke<K, false>(mode, grid, uin, uout, phi, lam, H, W, P, S, ncols, nwaves, c, s);
   DZ_CHECK_LAUNCH();
   return DEHAZE_OK;
 }
@@ -412,6 +505,10 @@ int launch_sweep_strip(int mode, int K, int S, const float* uin, float* uout, co
     set_error("strip sweep needs R = 2, S >= 1 and an update mode");
     return DEHAZE_EINVAL;
   }
+  if (!strip_fits(H, P)) {
+    set_error("plane of %d x %d elements exceeds the strip kernel's 32-bit byte offsets", H, P);
+    return DEHAZE_EINVAL;
+  }
   switch (K) {
     case 1: return launch_strip_k<1>(mode, uin, uout, phi, lam, H, W, P, S, c, s);
     case 2: return launch_strip_k<2>(mode, uin, uout, phi, lam, H, W, P, S, c, s);
@@ -420,6 +517,8 @@ int launch_sweep_strip(int mode, int K, int S, const float* uin, float* uout, co
     default: set_error("sweeps per launch %d outside 1..4", K); return DEHAZE_EINVAL;
   }
 }
+
+bool strip_fits(int H, int P) { return static_cast<long long>(H) * P * 4 < (1LL << 31); }
 
 int sweep_num_blocks(int H, int W) { return ((W + kTX - 1) / kTX) * ((H + kTY - 1) / kTY); }
 
