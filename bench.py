@@ -41,8 +41,8 @@ HBM_PEAK_GBS = 8000.0
 
 # HBM-side traffic of one sweep launch from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (KiB per dispatch), keyed by the hash of the kernel source the
-# counters were taken on and by the launch shape "KxS" (sweeps per launch x
-# strip rows).  A 128 MiB device-copy dispatch reads 65,544 KiB on FETCH_SIZE
+# counters were taken on and by the launch shape "KxSxC" (sweeps per launch,
+# strip rows, columns per lane).  A 128 MiB device-copy dispatch reads 65,544 KiB on FETCH_SIZE
 # and 131,072 KiB on WRITE_SIZE, so reads are scaled by 2.0 and writes by 1.0.
 # A different source hash reports null.
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
@@ -51,8 +51,8 @@ TRAFFIC_KIB = {
 }
 
 
-def traffic_bytes(khash: str, k: int, rows: int):
-    kib = TRAFFIC_KIB.get(khash, {}).get(f"{k}x{rows}")
+def traffic_bytes(khash: str, k: int, rows: int, cols: int):
+    kib = TRAFFIC_KIB.get(khash, {}).get(f"{k}x{rows}x{cols}")
     if kib is None:
         return None
     return round((kib[0] * FETCH_SCALE + kib[1] * WRITE_SCALE) * 1024)
@@ -148,6 +148,7 @@ def main() -> int:
     ap.add_argument("--calibrate-copy", action="store_true", help="also run a 256 MiB device copy")
     ap.add_argument("--sweeps-per-launch", type=int, default=0, help="pin K (default: the library's tuner)")
     ap.add_argument("--strip-rows", type=int, default=0, help="pin the strip height S (default: tuned)")
+    ap.add_argument("--lane-columns", type=int, default=0, help="pin the columns per lane C (default: tuned)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -163,7 +164,8 @@ def main() -> int:
     I = torch.from_numpy(img["I"]).cuda()
     p_prior = d.dehaze_params_default()
     p_solve = d.dehaze_params_default(scheme=d.JACOBI, max_outer=SWEEPS, rel_tol=0.0,
-                                      sweeps_per_launch=args.sweeps_per_launch, strip_rows=args.strip_rows)
+                                      sweeps_per_launch=args.sweeps_per_launch, strip_rows=args.strip_rows,
+                                      lane_columns=args.lane_columns)
     u = torch.empty((3, H, W), dtype=torch.float32, device="cuda")
     ws = d.solve_workspace(H, W, p_solve)
     stream = torch.cuda.current_stream()
@@ -192,10 +194,11 @@ def main() -> int:
     solve_ms = float(np.mean([a.elapsed_time(b) for a, b in events]))
     sweep_s = solve_ms / 1e3 / SWEEPS
     achieved = SWEEP_BYTES_PER_PIXEL * H * W / sweep_s / 1e9
-    k_launch, strip_rows = d.dehaze_sweep_shape(ctx, H, W, d.JACOBI)
-    if args.sweeps_per_launch > 0 or args.strip_rows > 0:
+    k_launch, strip_rows, lane_cols = d.dehaze_sweep_shape(ctx, H, W, d.JACOBI)
+    if args.sweeps_per_launch > 0 or args.strip_rows > 0 or args.lane_columns > 0:
         k_launch = args.sweeps_per_launch or k_launch or 2
         strip_rows = args.strip_rows or strip_rows or 32
+        lane_cols = args.lane_columns or lane_cols or 1
     k_launch = max(k_launch, 1)
 
     ms_per_step = elapsed / args.steps * 1e3
@@ -214,8 +217,9 @@ def main() -> int:
                    "eps": 1e-3},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic_bytes(khash, k_launch, strip_rows),
+                     "traffic": traffic_bytes(khash, k_launch, strip_rows, lane_cols),
                      "kernel": "k_sweep_strip (Jacobi)", "sweeps_per_launch": k_launch, "strip_rows": strip_rows,
+                     "lane_columns": lane_cols,
                      "kernel_avg_us": round(sweep_s * k_launch * 1e6, 3),
                      "bytes_per_launch": SWEEP_BYTES_PER_PIXEL * H * W * k_launch, "kernel_source": khash},
         "final_rel_residual": st["rel_residual"],

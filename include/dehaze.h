@@ -96,7 +96,8 @@ typedef struct dehaze_params {
                                at u_n, re-form Phi - L_{D(u_n)} u in float64 and solve again (0 = one solve) */
   int32_t strip_rows;       /* output rows per wavefront of the register-resident sweep kernel; 0 = the
                                tuned value (every value gives bit-identical results) */
-  int32_t reserved[4];      /* must be zero */
+  int32_t lane_columns;     /* adjacent columns per lane of that kernel (1 or 2); 0 = tuned */
+  int32_t reserved[3];      /* must be zero */
 } dehaze_params;
 
 typedef struct dehaze_stats {
@@ -239,10 +240,12 @@ int dehaze_cnn_grad(dehaze_ctx* ctx, int n, int H, int W, const float* I, const 
 int dehaze_cnn_train_step(dehaze_ctx* ctx, int n, int H, int W, const float* I, const float* t, const float* A,
                           const float* target, float lr, double* loss, void* ws, size_t ws_bytes, void* stream);
 
-/* Launch shape the context uses for explicit/Jacobi sweeps of an H x W
-   image: *sweeps_per_launch (0 if none has been chosen yet, or if the tile
-   kernel is used because g_radius != 2) and *strip_rows. */
-int dehaze_sweep_shape(const dehaze_ctx* ctx, int H, int W, int scheme, int* sweeps_per_launch, int* strip_rows);
+/* Launch shape the context's tuner chose for explicit/Jacobi sweeps of an
+   H x W image: *sweeps_per_launch (0 if none has been chosen yet, or if the
+   tile kernel is used because g_radius != 2 or a plane exceeds 2 GiB),
+   *strip_rows and *lane_columns.  Host pointers; EINVAL if any is NULL. */
+int dehaze_sweep_shape(const dehaze_ctx* ctx, int H, int W, int scheme, int* sweeps_per_launch, int* strip_rows,
+                       int* lane_columns);
 
 /* ------------------------------------------------------------ residual
  * rho = ||Phi - L_{D(u)} u||_2 / ||Phi||_2 over all channels, for planar

@@ -32,7 +32,8 @@ class Params(ctypes.Structure):
         ("scheme", c_int32), ("max_outer", c_int32), ("max_inner", c_int32), ("check_every", c_int32),
         ("atm_divisor", c_int32), ("warm_start", c_int32), ("nonlocal_term", c_int32),
         ("adaptive", c_int32), ("edge_preserving", c_int32), ("sweeps_per_launch", c_int32),
-        ("inner_refine", c_int32), ("strip_rows", c_int32), ("reserved", c_int32 * 4),
+        ("inner_refine", c_int32), ("strip_rows", c_int32), ("lane_columns", c_int32),
+        ("reserved", c_int32 * 3),
     ]
 
     def replace(self, **kw) -> "Params":
@@ -105,7 +106,7 @@ _SIGS = {
                                 POINTER(c_double), c_void_p, c_size_t, c_void_p]),
     "dehaze_cnn_train_step": (c_int, [c_void_p, c_int, c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p,
                                       ctypes.c_float, POINTER(c_double), c_void_p, c_size_t, c_void_p]),
-    "dehaze_sweep_shape": (c_int, [c_void_p, c_int, c_int, c_int, POINTER(c_int), POINTER(c_int)]),
+    "dehaze_sweep_shape": (c_int, [c_void_p, c_int, c_int, c_int, POINTER(c_int), POINTER(c_int), POINTER(c_int)]),
     "dehaze_residual_workspace_size": (c_size_t, [c_int, c_int, _P]),
     "dehaze_residual": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, _P, c_void_p,
                                 POINTER(c_double), c_void_p, c_size_t, c_void_p]),
@@ -371,7 +372,8 @@ def dehaze_cnn_train_step(ctx: Context, I, t, A, target, lr: float, ws=None, wan
 
 
 def dehaze_sweep_shape(ctx: Context, H: int, W: int, scheme: int = JACOBI):
-    """(sweeps per launch, strip rows) the context uses for H x W sweeps (0, 0 if none yet)."""
-    k, srows = c_int(), c_int()
-    _check(_lib.dehaze_sweep_shape(ctx.handle, H, W, scheme, ctypes.byref(k), ctypes.byref(srows)))
-    return k.value, srows.value
+    """(sweeps per launch, strip rows, columns per lane) the context's tuner
+    chose for H x W sweeps ((0, 0, 0) if none yet)."""
+    k, srows, cols = c_int(), c_int(), c_int()
+    _check(_lib.dehaze_sweep_shape(ctx.handle, H, W, scheme, ctypes.byref(k), ctypes.byref(srows), ctypes.byref(cols)))
+    return k.value, srows.value, cols.value

@@ -52,6 +52,7 @@ int check_params(const dehaze_params* p) {
   if (p->sweeps_per_launch < 0) { set_error("sweeps_per_launch must be >= 0"); return DEHAZE_EINVAL; }
   if (p->inner_refine < 0) { set_error("inner_refine must be >= 0"); return DEHAZE_EINVAL; }
   if (p->strip_rows < 0) { set_error("strip_rows must be >= 0"); return DEHAZE_EINVAL; }
+  if (p->lane_columns < 0 || p->lane_columns > 2) { set_error("lane_columns must be 0, 1 or 2"); return DEHAZE_EINVAL; }
   for (int r : p->reserved)
     if (r != 0) { set_error("reserved fields of dehaze_params must be zero"); return DEHAZE_EINVAL; }
   if (!(p->inner_rtol > 0.0)) { set_error("inner_rtol must be positive"); return DEHAZE_EINVAL; }
@@ -116,6 +117,7 @@ int dehaze_params_default(dehaze_params* p) {
   p->edge_preserving = 1;
   p->sweeps_per_launch = 0;
   p->strip_rows = 0;
+  p->lane_columns = 0;
   return DEHAZE_OK;
 }
 
@@ -320,10 +322,14 @@ int dehaze_cnn_train_step(dehaze_ctx* ctx, int n, int H, int W, const float* I, 
   return cnn_train_step(ctx->c, n, H, W, I, t, A, target, lr, loss, ws, static_cast<hipStream_t>(stream));
 }
 
-int dehaze_sweep_shape(const dehaze_ctx* ctx, int H, int W, int scheme, int* sweeps_per_launch, int* strip_rows) {
+int dehaze_sweep_shape(const dehaze_ctx* ctx, int H, int W, int scheme, int* sweeps_per_launch, int* strip_rows,
+                       int* lane_columns) {
   clear_error();
-  if (!ctx || !sweeps_per_launch || !strip_rows) { set_error("ctx and outputs are required"); return DEHAZE_EINVAL; }
-  return sweep_shape(ctx->c, H, W, scheme, sweeps_per_launch, strip_rows);
+  if (!ctx || !sweeps_per_launch || !strip_rows || !lane_columns) {
+    set_error("ctx and outputs are required");
+    return DEHAZE_EINVAL;
+  }
+  return sweep_shape(ctx->c, H, W, scheme, sweeps_per_launch, strip_rows, lane_columns);
 }
 
 size_t dehaze_residual_workspace_size(int H, int W, const dehaze_params* p) {

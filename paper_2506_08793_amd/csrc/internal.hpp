@@ -127,13 +127,19 @@ int sweep_num_blocks(int H, int W);
 int launch_sweep(int mode, const float* uin, float* uout, const float* phi, const float* lam,
                  int H, int W, int P, const OpConst& c, double* partials, hipStream_t s);
 // K (1..4) pipelined sweeps in one launch, register-resident strips of S
-// output rows (R = 2, explicit or Jacobi); uin and uout must differ.
+// output rows with C (1 or 2) columns per lane (R = 2, explicit or Jacobi);
+// uin and uout must differ.
 constexpr int kMaxSweepsPerLaunch = 4;
 // Whether a plane of H rows of pitch P is addressable by the strip kernel
 // (byte offsets below 2^31); larger planes use the tile kernel.
 bool strip_fits(int H, int P);
-int launch_sweep_strip(int mode, int K, int S, const float* uin, float* uout, const float* phi, const float* lam,
-                       int H, int W, int P, const OpConst& c, hipStream_t s);
+// Launch shape of the strip kernel: K sweeps per launch, S output rows per
+// wavefront, C adjacent columns per lane (a wavefront spans 64 C columns).
+struct StripShape {
+  int K = 0, S = 0, C = 0;
+};
+int launch_sweep_strip(int mode, int K, int S, int C, const float* uin, float* uout, const float* phi,
+                       const float* lam, int H, int W, int P, const OpConst& c, hipStream_t s);
 // Deterministic sum of `n` (a, b) double pairs into out[0..1].
 int launch_reduce_pairs(const double* partials, int n, double* out, hipStream_t s);
 

@@ -2,6 +2,7 @@
 // picks the starting iterate and runs the chosen fixed-point iteration
 // (Appendix A-1) with its stopping rule.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -61,10 +62,10 @@ int residual_of(const float* u, const SweepPlan& pl, int H, int W, const OpConst
 }  // namespace
 
 // Launch shape of the strip sweep kernel chosen per (H, W, mode): sweeps per
-// launch K and strip height S.  Every shape computes the same values, so the
-// choice only affects speed.
+// launch K, strip height S and columns per lane C.  Every shape computes the
+// same values, so the choice only affects speed.
 struct SweepTune {
-  std::map<std::tuple<int, int, int>, std::pair<int, int>> best;
+  std::map<std::tuple<int, int, int>, std::array<int, 3>> best;
 };
 
 namespace {
@@ -73,61 +74,82 @@ constexpr int kStripHeights[] = {8, 12, 16, 20, 24, 28, 32, 40, 48, 64, 96, 128}
 
 // Times every shape on sweeps from u to scratch (the caller's starting
 // iterate and the other half of its ping-pong pair), so the trial launches
-// touch the same buffers as the solve.
+// touch the same buffers as the solve.  A forced K, S or C (> 0) is taken as
+// given; the others come from the tuned shape when there is one, else from
+// defaults.
 int pick_strip_shape(Ctx& ctx, int mode, int H, int W, int P, const float* u, const float* phi, const float* lam,
-                     float* scratch, const OpConst& oc, int forced_k, int forced_s, hipStream_t s, int* K, int* S) {
-  *K = 0;
-  *S = 0;
+                     float* scratch, const OpConst& oc, const dehaze_params& p, hipStream_t s, StripShape* out) {
+  *out = StripShape{};
   if (oc.R != 2 || !strip_fits(H, P)) return DEHAZE_OK;  // the tile kernel handles these
   if (!ctx.tune) ctx.tune = new SweepTune();
   const auto key = std::make_tuple(H, W, mode);
   auto it = ctx.tune->best.find(key);
   const bool tuned = it != ctx.tune->best.end();
-  if (forced_k > 0 || forced_s > 0) {
-    *K = forced_k > 0 ? std::min(forced_k, kMaxSweepsPerLaunch) : (tuned ? it->second.first : 2);
-    *S = forced_s > 0 ? forced_s : (tuned ? it->second.second : 32);
+  if (p.sweeps_per_launch > 0 || p.strip_rows > 0 || p.lane_columns > 0) {
+    out->K = p.sweeps_per_launch > 0 ? std::min(p.sweeps_per_launch, kMaxSweepsPerLaunch) : (tuned ? it->second[0] : 2);
+    out->S = p.strip_rows > 0 ? p.strip_rows : (tuned ? it->second[1] : 32);
+    out->C = p.lane_columns > 0 ? p.lane_columns : (tuned ? it->second[2] : 1);
     return DEHAZE_OK;
   }
-  if (it != ctx.tune->best.end()) {
-    *K = it->second.first;
-    *S = it->second.second;
+  if (tuned) {
+    *out = StripShape{it->second[0], it->second[1], it->second[2]};
     return DEHAZE_OK;
   }
   hipEvent_t e0, e1;
   DZ_HIP(hipEventCreate(&e0));
   DZ_HIP(hipEventCreate(&e1));
   float best = 1e30f;
-  int bk = 1, bs = 32;
+  StripShape bst{1, 32, 1};
   int rc = DEHAZE_OK;
-  for (int k = 1; k <= kMaxSweepsPerLaunch && rc == DEHAZE_OK; ++k) {
-    int prev_strips = -1;
-    for (int sh : kStripHeights) {
-      // heights that give the same strip count as the previous one add nothing
-      const int strips = (H + sh - 1) / sh;
-      if (strips == prev_strips) continue;
-      prev_strips = strips;
-      if ((rc = launch_sweep_strip(mode, k, sh, u, scratch, phi, lam, H, W, P, oc, s))) break;
-      if (hipEventRecord(e0, s) != hipSuccess) { rc = DEHAZE_EHIP; break; }
-      for (int i = 0; i < 3 && rc == DEHAZE_OK; ++i) rc = launch_sweep_strip(mode, k, sh, u, scratch, phi, lam, H, W, P, oc, s);
-      if (rc) break;
-      if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { rc = DEHAZE_EHIP; break; }
-      float ms = 0.0f;
-      if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = DEHAZE_EHIP; break; }
-      const float per_sweep = ms / (3.0f * k);
-      if (per_sweep < best) {
-        best = per_sweep;
-        bk = k;
-        bs = sh;
+  for (int c = 1; c <= 2 && rc == DEHAZE_OK; ++c) {
+    for (int k = 1; k <= kMaxSweepsPerLaunch && rc == DEHAZE_OK; ++k) {
+      int prev_strips = -1;
+      for (int sh : kStripHeights) {
+        // heights that give the same strip count as the previous one add nothing
+        const int strips = (H + sh - 1) / sh;
+        if (strips == prev_strips) continue;
+        prev_strips = strips;
+        if ((rc = launch_sweep_strip(mode, k, sh, c, u, scratch, phi, lam, H, W, P, oc, s))) break;
+        if (hipEventRecord(e0, s) != hipSuccess) { rc = DEHAZE_EHIP; break; }
+        for (int i = 0; i < 3 && rc == DEHAZE_OK; ++i)
+          rc = launch_sweep_strip(mode, k, sh, c, u, scratch, phi, lam, H, W, P, oc, s);
+        if (rc) break;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { rc = DEHAZE_EHIP; break; }
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = DEHAZE_EHIP; break; }
+        const float per_sweep = ms / (3.0f * k);
+        if (per_sweep < best) {
+          best = per_sweep;
+          bst = StripShape{k, sh, c};
+        }
       }
+    }
+  }
+  // refine the strip height around the winner: the balance of wavefronts
+  // over the compute units changes quickly with the strip count
+  const StripShape coarse = bst;
+  for (int sh = std::max(4, coarse.S - 3); sh <= coarse.S + 3 && rc == DEHAZE_OK; ++sh) {
+    if (sh == coarse.S) continue;
+    if ((rc = launch_sweep_strip(mode, coarse.K, sh, coarse.C, u, scratch, phi, lam, H, W, P, oc, s))) break;
+    if (hipEventRecord(e0, s) != hipSuccess) { rc = DEHAZE_EHIP; break; }
+    for (int i = 0; i < 3 && rc == DEHAZE_OK; ++i)
+      rc = launch_sweep_strip(mode, coarse.K, sh, coarse.C, u, scratch, phi, lam, H, W, P, oc, s);
+    if (rc) break;
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { rc = DEHAZE_EHIP; break; }
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = DEHAZE_EHIP; break; }
+    const float per_sweep = ms / (3.0f * coarse.K);
+    if (per_sweep < best) {
+      best = per_sweep;
+      bst = StripShape{coarse.K, sh, coarse.C};
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc == DEHAZE_EHIP) set_error("timing the sweep launch shapes failed");
   if (rc) return rc;
-  ctx.tune->best[key] = {bk, bs};
-  *K = bk;
-  *S = bs;
+  ctx.tune->best[key] = {bst.K, bst.S, bst.C};
+  *out = bst;
   return DEHAZE_OK;
 }
 
@@ -144,17 +166,16 @@ int run_sweeps(Ctx& ctx, const SolveArgs& a, const dehaze_params& p, dehaze_stat
 
   const OpConst oc = make_opconst(p);
   const int mode = p.scheme == DEHAZE_PAPER_EXPLICIT ? kExplicit : kJacobi;
-  int K = 0, S = 0;
-  if ((rc = pick_strip_shape(ctx, mode, H, W, pl.P, pl.ua, pl.phi, pl.lam, pl.ub, oc, p.sweeps_per_launch, p.strip_rows, s,
-                             &K, &S)))
-    return rc;
+  StripShape sh;
+  if ((rc = pick_strip_shape(ctx, mode, H, W, pl.P, pl.ua, pl.phi, pl.lam, pl.ub, oc, p, s, &sh))) return rc;
+  const int K = sh.K;
   float* cur = pl.ua;
   float* nxt = pl.ub;
   // n sweeps from cur, ending with the result in cur
   auto sweeps = [&](int n) -> int {
     while (n > 0) {
       const int k = K > 0 ? std::min(K, n) : 1;
-      const int e = K > 0 ? launch_sweep_strip(mode, k, S, cur, nxt, pl.phi, pl.lam, H, W, pl.P, oc, s)
+      const int e = K > 0 ? launch_sweep_strip(mode, k, sh.S, sh.C, cur, nxt, pl.phi, pl.lam, H, W, pl.P, oc, s)
                           : launch_sweep(mode, cur, nxt, pl.phi, pl.lam, H, W, pl.P, oc, nullptr, s);
       if (e) return e;
       std::swap(cur, nxt);
@@ -506,15 +527,15 @@ int solve_one(Ctx& ctx, const SolveArgs& a, const dehaze_params& p, dehaze_stats
   return run_sweeps(ctx, a, p, st, s);
 }
 
-int sweep_shape(const Ctx& ctx, int H, int W, int scheme, int* K, int* S) {
-  *K = 0;
-  *S = 0;
+int sweep_shape(const Ctx& ctx, int H, int W, int scheme, int* K, int* S, int* C) {
+  *K = *S = *C = 0;
   if (!ctx.tune) return DEHAZE_OK;
   const int mode = scheme == DEHAZE_PAPER_EXPLICIT ? kExplicit : kJacobi;
   auto it = ctx.tune->best.find(std::make_tuple(H, W, mode));
   if (it != ctx.tune->best.end()) {
-    *K = it->second.first;
-    *S = it->second.second;
+    *K = it->second[0];
+    *S = it->second[1];
+    *C = it->second[2];
   }
   return DEHAZE_OK;
 }

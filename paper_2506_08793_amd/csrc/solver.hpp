@@ -19,7 +19,7 @@ struct SolveArgs {
 size_t solver_workspace_bytes(int H, int W, const dehaze_params& p);
 int solve_one(Ctx& ctx, const SolveArgs& a, const dehaze_params& p, dehaze_stats* stats, hipStream_t s);
 void solver_release(Ctx& ctx);
-int sweep_shape(const Ctx& ctx, int H, int W, int scheme, int* K, int* S);
+int sweep_shape(const Ctx& ctx, int H, int W, int scheme, int* K, int* S, int* C);
 size_t batch_workspace_bytes(int n, const dehaze_image* imgs, const dehaze_params& p);
 int solve_batch(Ctx& ctx, int n, const dehaze_image* imgs, int dtype, int layout, const dehaze_params& p, void* ws,
                 dehaze_stats* st, hipStream_t s);

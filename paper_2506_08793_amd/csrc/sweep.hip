@@ -264,14 +264,16 @@ __device__ __forceinline__ float keep_lanes(float out, unsigned long long live) 
   return r;
 }
 
-// Register state of one sweep level: windows over the last four rows it
-// received (rows j-2 .. j+1 when it is about to produce row j), the flux and
-// coefficient of the face above row j, and its Phi / lambda prefetch rings.
-template <int PF>
+// Register state of one sweep level, per column c of the lane: windows over
+// the last four rows it received (rows j-2 .. j+1 when it is about to
+// produce row j) of u, of its left and right neighbours and of the
+// horizontal Gaussian pass; the flux and coefficient of the face above row
+// j; and its Phi / lambda prefetch rings.
+template <int C, int PF>
 struct StripLevel {
-  float U[4], SL[4], SR[4], GH[4];
-  float qT, DT;
-  float ph[PF], la[PF];
+  float U[C][4], SL[C][4], SR[C][4], GH[C][4];
+  float qT[C], DT[C];
+  float ph[C][PF], la[C][PF];
 };
 
 struct StripConst {
@@ -285,61 +287,105 @@ __device__ __forceinline__ float strip_face(float gn, float gt, float eps) {
   return EDGE ? __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(__builtin_fmaf(gn, gn, gt * gt)) + eps) : 1.0f;
 }
 
-// One row step of level L: takes the level's input row v (row j + 2), shifts
-// the windows and, when ACTIVE, returns the updated value of row j.  FIRST
-// marks the level's first active row, whose top face is formed from the
-// windows instead of the previous row.
-template <int MODE, bool EDGE, bool ACTIVE, bool FIRST, int PF>
-__device__ __forceinline__ float strip_level(StripLevel<PF>& L, float v, int q, const StripConst& k) {
+// Values at column offset d (-2..2) of every column of the lane: columns
+// c + d inside the lane are registers, the others come from the neighbouring
+// lane (one shift, or two when a lane holds a single column).
+template <int C>
+struct Shifted {
+  float l1[C], r1[C], l2[C], r2[C];
+  __device__ __forceinline__ explicit Shifted(const float (&v)[C]) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      l1[c] = from_left(v[c]);
+      r1[c] = from_right(v[c]);
+    }
+    if (C == 1) {
+      l2[0] = from_left(l1[0]);
+      r2[0] = from_right(r1[0]);
+    }
+  }
+  __device__ __forceinline__ float at(const float (&v)[C], int c, int d) const {
+    const int sc = c + d;
+    if (sc >= 0 && sc < C) return v[sc];
+    if (sc < 0) return sc >= -C ? l1[sc + C] : l2[sc + 2 * C];
+    return sc < 2 * C ? r1[sc - C] : r2[sc - 2 * C];
+  }
+};
+
+// One row step of level L: takes the level's input row v (row j + 2, one
+// value per column of the lane), shifts the windows and, when ACTIVE,
+// returns the updated values of row j.  FIRST marks the level's first active
+// row, whose top face is formed from the windows instead of the previous row.
+template <int C, int MODE, bool EDGE, bool ACTIVE, bool FIRST, int PF>
+__device__ __forceinline__ void strip_level(StripLevel<C, PF>& L, const float (&v)[C], float (&out)[C], int q,
+                                            const StripConst& k) {
 #pragma clang fp contract(off)
-  const float sl1 = from_left(v), sr1 = from_right(v);
-  const float sl2 = from_left(sl1), sr2 = from_right(sr1);
-  const float ghn = __builtin_fmaf(k.w2, sl2 + sr2, __builtin_fmaf(k.w1, sl1 + sr1, k.w0 * v));
-  float out = 0.0f;
+  const Shifted<C> sh(v);
+  float ghn[C], sl1[C], sr1[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    sl1[c] = sh.at(v, c, -1);
+    sr1[c] = sh.at(v, c, 1);
+    ghn[c] = __builtin_fmaf(k.w2, sh.at(v, c, -2) + sh.at(v, c, 2), __builtin_fmaf(k.w1, sl1[c] + sr1[c], k.w0 * v[c]));
+    out[c] = 0.0f;
+  }
   if (ACTIVE) {
-    const float up = L.U[1], u0 = L.U[2], dn = L.U[3];
-    if (FIRST) {
-      const float gny_t = u0 - up;
-      const float gty_t = 0.5f * (L.SR[1] - L.SL[1]);
-      L.DT = strip_face<EDGE>(gny_t, gty_t, k.eps);
-      L.qT = L.DT * gny_t;
+    float DR[C], qR[C], DB[C], qB[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const float up = L.U[c][1], u0 = L.U[c][2], dn = L.U[c][3];
+      if (FIRST) {
+        const float gny_t = u0 - up;
+        const float gty_t = 0.5f * (L.SR[c][1] - L.SL[c][1]);
+        L.DT[c] = strip_face<EDGE>(gny_t, gty_t, k.eps);
+        L.qT[c] = L.DT[c] * gny_t;
+      }
+      // face right of (x, j): normal u(x+1) - u(x), tangential at this cell
+      const float gnx = L.SR[c][2] - u0;
+      const float gtx = 0.5f * (dn - up);
+      DR[c] = strip_face<EDGE>(gnx, gtx, k.eps);
+      qR[c] = DR[c] * gnx;
+      // face below (x, j): normal u(j+1) - u(j), tangential at this cell
+      const float gny = dn - u0;
+      const float gty = 0.5f * (L.SR[c][2] - L.SL[c][2]);
+      DB[c] = strip_face<EDGE>(gny, gty, k.eps);
+      qB[c] = DB[c] * gny;
     }
-    const float G = __builtin_fmaf(k.w2, L.GH[0] + ghn, __builtin_fmaf(k.w1, L.GH[1] + L.GH[3], k.w0 * L.GH[2]));
-    // face right of (x, j): normal u(x+1) - u(x), tangential at this cell
-    const float gnx = L.SR[2] - u0;
-    const float gtx = 0.5f * (dn - up);
-    const float DR = strip_face<EDGE>(gnx, gtx, k.eps);
-    const float qR = DR * gnx;
-    const float DL = from_left(DR), qL = from_left(qR);
-    // face below (x, j): normal u(j+1) - u(j), tangential at this cell
-    const float gny = dn - u0;
-    const float gty = 0.5f * (L.SR[2] - L.SL[2]);
-    const float DB = strip_face<EDGE>(gny, gty, k.eps);
-    const float qB = DB * gny;
-    const float div = (qR - qL) + (qB - L.qT);
-    const float phc = L.ph[q], lac = L.la[q];
-    const float r_ = phc - __builtin_fmaf(lac, G, -div);
-    if (MODE == kExplicit) {
-      out = __builtin_fmaf(k.tau, r_, u0);
-    } else {
-      const float d = __builtin_fmaf(lac, k.wc2, (DL + DR) + (L.DT + DB));
-      out = __builtin_fmaf(k.theta * r_, __builtin_amdgcn_rcpf(d), u0);
+    // the face left of column 0 is the right face of the left lane's last column
+    const float DLx = from_left(DR[C - 1]), qLx = from_left(qR[C - 1]);
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const float u0 = L.U[c][2];
+      const float DL = c > 0 ? DR[c - 1] : DLx, qL = c > 0 ? qR[c - 1] : qLx;
+      const float G =
+          __builtin_fmaf(k.w2, L.GH[c][0] + ghn[c], __builtin_fmaf(k.w1, L.GH[c][1] + L.GH[c][3], k.w0 * L.GH[c][2]));
+      const float div = (qR[c] - qL) + (qB[c] - L.qT[c]);
+      const float phc = L.ph[c][q], lac = L.la[c][q];
+      const float r_ = phc - __builtin_fmaf(lac, G, -div);
+      if (MODE == kExplicit) {
+        out[c] = __builtin_fmaf(k.tau, r_, u0);
+      } else {
+        const float d = __builtin_fmaf(lac, k.wc2, (DL + DR[c]) + (L.DT[c] + DB[c]));
+        out[c] = __builtin_fmaf(k.theta * r_, __builtin_amdgcn_rcpf(d), u0);
+      }
+      L.qT[c] = qB[c];
+      L.DT[c] = DB[c];
     }
-    L.qT = qB;
-    L.DT = DB;
   }
 #pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    L.U[i] = L.U[i + 1];
-    L.SL[i] = L.SL[i + 1];
-    L.SR[i] = L.SR[i + 1];
-    L.GH[i] = L.GH[i + 1];
+  for (int c = 0; c < C; ++c) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      L.U[c][i] = L.U[c][i + 1];
+      L.SL[c][i] = L.SL[c][i + 1];
+      L.SR[c][i] = L.SR[c][i + 1];
+      L.GH[c][i] = L.GH[c][i + 1];
+    }
+    L.U[c][3] = v[c];
+    L.SL[c][3] = sl1[c];
+    L.SR[c][3] = sr1[c];
+    L.GH[c][3] = ghn[c];
   }
-  L.U[3] = v;
-  L.SL[3] = sl1;
-  L.SR[3] = sr1;
-  L.GH[3] = ghn;
-  return out;
 }
 
 // Sweep level s lags level s - 1 by two rows and must produce rows
@@ -348,34 +394,43 @@ __device__ __forceinline__ float strip_level(StripLevel<PF>& L, float v, int q, 
 // (steps 4b .. 4b+3, b = 0..K) levels 0 .. b-1 are active, and after the
 // head every level is.  The walk ends with the last level at row y1 - 1.
 // Rows of the earlier levels beyond their range are computed and unused.
-template <int K, int MODE, bool EDGE>
+// A lane holds C adjacent columns; a wavefront covers 64 C columns, of which
+// 2K on either side are halo.
+template <int K, int C, int MODE, bool EDGE>
 __global__ __launch_bounds__(256) void k_sweep_strip(const float* __restrict__ uin, float* __restrict__ uout,
                                                       const float* __restrict__ phi, const float* __restrict__ lam,
                                                       int H, int W, int P, int S, int ncols, int nwaves, OpConst oc) {
 #pragma clang fp contract(off)
-  constexpr int OW = 64 - 4 * K;
+  constexpr int OW = 64 * C - 4 * K;
   constexpr int PF = 4;  // rows in flight; also the unroll of the walk
   const int lane = threadIdx.x & 63;
   // the wavefront index is uniform: keep everything derived from it scalar
   const int gw = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (gw >= nwaves) return;  // uniform per wavefront
-  const int c = gw % 3;
+  const int ch = gw % 3;
   const int rest = gw / 3;
   const int col = rest % ncols, strip = rest / ncols;
-  const int x = col * OW - 2 * K + lane;
-  const bool xin = x >= 0 && x < W;
-  const unsigned long long live = __builtin_amdgcn_ballot_w64(xin);
+  const int x0 = col * OW - 2 * K + C * lane;  // column of the lane's first value
   const int y0 = strip * S;
   const int y1 = min(y0 + S, H);
   const int rs = y0 - 2 * K;  // first input row of the walk
-  const bool out_lane = lane >= 2 * K && lane < 2 * K + OW && xin;
   const unsigned plane_bytes = static_cast<unsigned>(H) * P * 4u;
   const size_t plane = static_cast<size_t>(H) * P;
-  const __amdgpu_buffer_rsrc_t ru = plane_rsrc(uin + c * plane, plane_bytes);
-  const __amdgpu_buffer_rsrc_t rp = plane_rsrc(phi + c * plane, plane_bytes);
+  const __amdgpu_buffer_rsrc_t ru = plane_rsrc(uin + ch * plane, plane_bytes);
+  const __amdgpu_buffer_rsrc_t rp = plane_rsrc(phi + ch * plane, plane_bytes);
   const __amdgpu_buffer_rsrc_t rl = plane_rsrc(lam, plane_bytes);
-  const __amdgpu_buffer_rsrc_t ro = plane_rsrc(uout + c * plane, plane_bytes);
-  const int voff = min(max(x, 0), W - 1) * 4;
+  const __amdgpu_buffer_rsrc_t ro = plane_rsrc(uout + ch * plane, plane_bytes);
+  int voff[C];
+  bool out_col[C];
+  unsigned long long live[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int x = x0 + c;
+    const bool xin = x >= 0 && x < W;
+    voff[c] = min(max(x, 0), W - 1) * 4;
+    live[c] = __builtin_amdgcn_ballot_w64(xin);
+    out_col[c] = xin && x >= col * OW && x < (col + 1) * OW;
+  }
   StripConst k;
   // without the nonlocal term every Gaussian weight is zero, so lambda G(u)
   // and its diagonal vanish
@@ -388,66 +443,86 @@ __global__ __launch_bounds__(256) void k_sweep_strip(const float* __restrict__ u
   k.theta = oc.theta;
   k.tau = oc.tau;
 
-  // Loads are unconditional from clamped rows; u of a row or column outside
-  // the image is zeroed with a bit mask (a select would be turned back into a
-  // branch around the load).  Phi and lambda need no mask: every value
-  // computed from them for a ghost cell is masked before it is used.
+  // Loads are unconditional from clamped rows and columns.  u of a row or
+  // column outside the image is zeroed when it is consumed; Phi and lambda
+  // need no mask, since every value computed from them for a ghost cell is
+  // masked before it is used.
   auto soff = [&](int r) { return min(max(r, 0), H - 1) * P * 4; };
-  // u of a row or column outside the image is zeroed when it is consumed
-  auto load_u = [&](int r) -> float {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(ru, voff, soff(r), 0));
-  };
-  auto load_f = [&](__amdgpu_buffer_rsrc_t rs_, int j) -> float {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs_, voff, soff(j), 0));
+  auto load = [&](__amdgpu_buffer_rsrc_t rs_, int c, int row) -> float {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs_, voff[c], soff(row), 0));
   };
 
-  StripLevel<PF> lv[K];
-  float qv[PF];
+  StripLevel<C, PF> lv[K];
+  float qv[C][PF];
 #pragma unroll
   for (int s = 0; s < K; ++s) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) lv[s].U[i] = lv[s].SL[i] = lv[s].SR[i] = lv[s].GH[i] = 0.0f;
-    lv[s].qT = lv[s].DT = 0.0f;
+    for (int c = 0; c < C; ++c) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) lv[s].U[c][i] = lv[s].SL[c][i] = lv[s].SR[c][i] = lv[s].GH[c][i] = 0.0f;
+      lv[s].qT[c] = lv[s].DT[c] = 0.0f;
+    }
   }
-  // step r serves level s with Phi / lambda of row r - 2(s + 1)
+  // step r serves level s with Phi / lambda of row r - 2(s + 1); a load
+  // issued at step r fills the ring slot that step r + PF - 1 reads
 #pragma unroll
   for (int q = 0; q < PF - 1; ++q) {
-    qv[q] = load_u(rs + q);
 #pragma unroll
-    for (int s = 0; s < K; ++s) {
-      lv[s].ph[q] = load_f(rp, rs + q - 2 * (s + 1));
-      lv[s].la[q] = load_f(rl, rs + q - 2 * (s + 1));
+    for (int c = 0; c < C; ++c) {
+      qv[c][q] = load(ru, c, rs + q);
+#pragma unroll
+      for (int s = 0; s < K; ++s) {
+        lv[s].ph[c][q] = load(rp, c, rs + q - 2 * (s + 1));
+        lv[s].la[c][q] = load(rl, c, rs + q - 2 * (s + 1));
+      }
     }
   }
 
-  // One row step; levels >= NACT only shift their windows.  Outputs of
-  // levels below K - 1 feed the next level and are zeroed outside the image;
-  // the last level stores rows [y0, y1) of its own lanes.
-  auto step = [&](auto nact_c, auto first_c, int r, int q) {
+  // One row step: levels below NACT are active, level NACT only fills its
+  // windows, the levels above it wait.  Outputs of levels below K - 1 feed
+  // the next level and are zeroed outside the image; the last level stores
+  // rows [y0, y1) of the lane's output columns.
+  auto step = [&](auto nact_c, auto first_c, int r, int q) __attribute__((always_inline)) {
     constexpr int NACT = decltype(nact_c)::value;
     constexpr int FIRSTLV = decltype(first_c)::value;  // level whose first row this is, or -1
-    float v = keep_lanes(qv[q], (r >= 0 && r < H) ? live : 0ull);
-    qv[(q + PF - 1) % PF] = load_u(r + PF - 1);
+    const bool row_in = r >= 0 && r < H;
+    float v[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      v[c] = keep_lanes(qv[c][q], row_in ? live[c] : 0ull);
+      qv[c][(q + PF - 1) % PF] = load(ru, c, r + PF - 1);
+    }
 #pragma unroll
     for (int s = 0; s < K; ++s) {
       const int j = r - 2 * (s + 1);
-      float out;
+      float out[C];
       if (s < NACT) {
-        if (s == FIRSTLV) out = strip_level<MODE, EDGE, true, true>(lv[s], v, q, k);
-        else out = strip_level<MODE, EDGE, true, false>(lv[s], v, q, k);
+        if (s == FIRSTLV) strip_level<C, MODE, EDGE, true, true>(lv[s], v, out, q, k);
+        else strip_level<C, MODE, EDGE, true, false>(lv[s], v, out, q, k);
       } else {
-        out = strip_level<MODE, EDGE, false, false>(lv[s], v, q, k);
+        if (s == NACT) strip_level<C, MODE, EDGE, false, false>(lv[s], v, out, q, k);
+#pragma unroll
+        for (int c = 0; c < C; ++c) out[c] = 0.0f;
       }
-      lv[s].ph[(q + PF - 1) % PF] = load_f(rp, r + PF - 1 - 2 * (s + 1));
-      lv[s].la[(q + PF - 1) % PF] = load_f(rl, r + PF - 1 - 2 * (s + 1));
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        lv[s].ph[c][(q + PF - 1) % PF] = load(rp, c, r + PF - 1 - 2 * (s + 1));
+        lv[s].la[c][(q + PF - 1) % PF] = load(rl, c, r + PF - 1 - 2 * (s + 1));
+      }
       if (s < NACT) {
         if (s < K - 1) {
-          out = keep_lanes(out, (j >= 0 && j < H) ? live : 0ull);
+          const bool jin = j >= 0 && j < H;
+#pragma unroll
+          for (int c = 0; c < C; ++c) out[c] = keep_lanes(out[c], jin ? live[c] : 0ull);
         } else if (j >= y0 && j < y1) {
-          if (out_lane) __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, out), ro, voff, j * P * 4, 0);
+#pragma unroll
+          for (int c = 0; c < C; ++c)
+            if (out_col[c])
+              __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, out[c]), ro, voff[c], j * P * 4, 0);
         }
       }
-      v = out;
+#pragma unroll
+      for (int c = 0; c < C; ++c) v[c] = out[c];
     }
   };
   // head: block b (0..K) has levels 0 .. b-1 active, level b-1 from its first
@@ -470,50 +545,54 @@ __global__ __launch_bounds__(256) void k_sweep_strip(const float* __restrict__ u
   }
 }
 
-template <int K, bool EDGE>
+template <int K, int C, bool EDGE>
 void launch_strip_ke(int mode, dim3 grid, const float* uin, float* uout, const float* phi, const float* lam, int H,
                      int W, int P, int S, int ncols, int nwaves, const OpConst& c, hipStream_t s) {
   if (mode == kExplicit)
-    hipLaunchKernelGGL((k_sweep_strip<K, kExplicit, EDGE>), grid, dim3(256), 0, s, uin, uout, phi, lam, H, W, P, S,
-                       ncols, nwaves, c);
+    hipLaunchKernelGGL((k_sweep_strip<K, C, kExplicit, EDGE>), grid, dim3(256), 0, s, uin, uout, phi, lam, H, W, P,
+                       S, ncols, nwaves, c);
   else
-    hipLaunchKernelGGL((k_sweep_strip<K, kJacobi, EDGE>), grid, dim3(256), 0, s, uin, uout, phi, lam, H, W, P, S,
-                       ncols, nwaves, c);
+    hipLaunchKernelGGL((k_sweep_strip<K, C, kJacobi, EDGE>), grid, dim3(256), 0, s, uin, uout, phi, lam, H, W, P,
+                       S, ncols, nwaves, c);
 }
 
-template <int K>
+template <int K, int C>
 int launch_strip_k(int mode, const float* uin, float* uout, const float* phi, const float* lam, int H, int W, int P,
                    int S, const OpConst& c, hipStream_t s) {
-  constexpr int OW = 64 - 4 * K;
+  constexpr int OW = 64 * C - 4 * K;
   const int ncols = (W + OW - 1) / OW;
   const int nstrips = (H + S - 1) / S;
   const int nwaves = 3 * ncols * nstrips;
   dim3 grid((nwaves + 3) / 4);
   if (c.edge_preserving)
-    launch_strip_ke<K, true>(mode, grid, uin, uout, phi, lam, H, W, P, S, ncols, nwaves, c, s);
+    launch_strip_ke<K, C, true>(mode, grid, uin, uout, phi, lam, H, W, P, S, ncols, nwaves, c, s);
   else
-    launch_strip_ke<K, false>(mode, grid, uin, uout, phi, lam, H, W, P, S, ncols, nwaves, c, s);
+    launch_strip_ke<K, C, false>(mode, grid, uin, uout, phi, lam, H, W, P, S, ncols, nwaves, c, s);
   DZ_CHECK_LAUNCH();
   return DEHAZE_OK;
 }
 
 }  // namespace
 
-int launch_sweep_strip(int mode, int K, int S, const float* uin, float* uout, const float* phi, const float* lam,
-                       int H, int W, int P, const OpConst& c, hipStream_t s) {
-  if (c.R != 2 || S < 1 || (mode != kExplicit && mode != kJacobi)) {
-    set_error("strip sweep needs R = 2, S >= 1 and an update mode");
+int launch_sweep_strip(int mode, int K, int S, int C, const float* uin, float* uout, const float* phi,
+                       const float* lam, int H, int W, int P, const OpConst& c, hipStream_t s) {
+  if (c.R != 2 || S < 1 || (mode != kExplicit && mode != kJacobi) || (C != 1 && C != 2)) {
+    set_error("strip sweep needs R = 2, S >= 1, 1 or 2 columns per lane and an update mode");
     return DEHAZE_EINVAL;
   }
   if (!strip_fits(H, P)) {
     set_error("plane of %d x %d elements exceeds the strip kernel's 32-bit byte offsets", H, P);
     return DEHAZE_EINVAL;
   }
-  switch (K) {
-    case 1: return launch_strip_k<1>(mode, uin, uout, phi, lam, H, W, P, S, c, s);
-    case 2: return launch_strip_k<2>(mode, uin, uout, phi, lam, H, W, P, S, c, s);
-    case 3: return launch_strip_k<3>(mode, uin, uout, phi, lam, H, W, P, S, c, s);
-    case 4: return launch_strip_k<4>(mode, uin, uout, phi, lam, H, W, P, S, c, s);
+  switch (K * 2 + (C - 1)) {
+    case 2: return launch_strip_k<1, 1>(mode, uin, uout, phi, lam, H, W, P, S, c, s);
+    case 3: return launch_strip_k<1, 2>(mode, uin, uout, phi, lam, H, W, P, S, c, s);
+    case 4: return launch_strip_k<2, 1>(mode, uin, uout, phi, lam, H, W, P, S, c, s);
+    case 5: return launch_strip_k<2, 2>(mode, uin, uout, phi, lam, H, W, P, S, c, s);
+    case 6: return launch_strip_k<3, 1>(mode, uin, uout, phi, lam, H, W, P, S, c, s);
+    case 7: return launch_strip_k<3, 2>(mode, uin, uout, phi, lam, H, W, P, S, c, s);
+    case 8: return launch_strip_k<4, 1>(mode, uin, uout, phi, lam, H, W, P, S, c, s);
+    case 9: return launch_strip_k<4, 2>(mode, uin, uout, phi, lam, H, W, P, S, c, s);
     default: set_error("sweeps per launch %d outside 1..4", K); return DEHAZE_EINVAL;
   }
 }

@@ -109,7 +109,8 @@ def test_prior_rejects_bad_arguments():
     require_gpu()
     import paper_2506_08793_amd as d
     img = dev(synth.hazy_image(8, 8, 1)["I"])
-    for kw in ({"patch": 4}, {"patch": 33}, {"t0": 0.0}, {"eps": -1.0}, {"omega": 1.5}, {"strip_rows": -1}):
+    for kw in ({"patch": 4}, {"patch": 33}, {"t0": 0.0}, {"eps": -1.0}, {"omega": 1.5}, {"strip_rows": -1},
+               {"lane_columns": 3}):
         with pytest.raises(d.DehazeError) as e:
             d.dehaze_prior(ctx(), img, params=d.dehaze_params_default(**kw))
         assert e.value.code == -1

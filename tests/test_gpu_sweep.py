@@ -124,22 +124,24 @@ def test_jacobi_full_megapixel_workload():
     assert rho_close(st["rel_residual"], ref.rho[-1], 1e-4)
 
 
+@pytest.mark.parametrize("cols", [1, 2])
 @pytest.mark.parametrize("k", [1, 2, 3, 4])
 @pytest.mark.parametrize("H,W,seed", [(37, 53, 60), (130, 67, 61), (1, 1, 62), (5, 300, 63), (64, 64, 1000)])
-def test_sweeps_per_launch_parity_and_invariance(k, H, W, seed):
+def test_sweeps_per_launch_parity_and_invariance(k, cols, H, W, seed):
     # K sweeps pipelined in one launch: same values as the oracle's sweeps, and
-    # bit for bit the same as one sweep per launch
+    # bit for bit the same as one sweep per launch with one column per lane
     require_gpu()
     I, t32, A32, lam, phi = _inputs(H, W, seed)
     n = 13
-    say(f"jacobi K={k} H={H} W={W}")
-    u, st = _gpu_solve(I, t32, A32, scheme=1, max_outer=n, rel_tol=0.0, sweeps_per_launch=k)
-    u1, _ = _gpu_solve(I, t32, A32, scheme=1, max_outer=n, rel_tol=0.0, sweeps_per_launch=1)
+    say(f"jacobi K={k} C={cols} H={H} W={W}")
+    u, st = _gpu_solve(I, t32, A32, scheme=1, max_outer=n, rel_tol=0.0, sweeps_per_launch=k, lane_columns=cols)
+    u1, _ = _gpu_solve(I, t32, A32, scheme=1, max_outer=n, rel_tol=0.0, sweeps_per_launch=1, lane_columns=1)
     assert np.array_equal(u, u1)
     # strip heights, including ones that are not a multiple of the 4-row
     # unroll and ones taller than the image
     for rows in (3, 6, 13, 40, 300):
-        us, _ = _gpu_solve(I, t32, A32, scheme=1, max_outer=n, rel_tol=0.0, sweeps_per_launch=k, strip_rows=rows)
+        us, _ = _gpu_solve(I, t32, A32, scheme=1, max_outer=n, rel_tol=0.0, sweeps_per_launch=k, strip_rows=rows,
+                           lane_columns=cols)
         assert np.array_equal(us, u1), rows
     ref = o.solve(phi, lam, "jacobi", steps=n)
     assert np.max(np.abs(u - ref.u)) <= U_TOL
@@ -148,8 +150,9 @@ def test_sweeps_per_launch_parity_and_invariance(k, H, W, seed):
     # two steps in one launch must equal two launches of one step exactly
     ue1, _ = _gpu_solve(I, t32, A32, scheme=0, max_outer=1, rel_tol=0.0, sweeps_per_launch=1)
     assert np.max(np.abs(ue1 - o.solve(phi, lam, "explicit", steps=1).u)) <= U_TOL
-    ue2, _ = _gpu_solve(I, t32, A32, scheme=0, max_outer=2, rel_tol=0.0, sweeps_per_launch=min(k, 2))
-    ue2b, _ = _gpu_solve(I, t32, A32, scheme=0, max_outer=2, rel_tol=0.0, sweeps_per_launch=1)
+    ue2, _ = _gpu_solve(I, t32, A32, scheme=0, max_outer=2, rel_tol=0.0, sweeps_per_launch=min(k, 2),
+                        lane_columns=cols)
+    ue2b, _ = _gpu_solve(I, t32, A32, scheme=0, max_outer=2, rel_tol=0.0, sweeps_per_launch=1, lane_columns=1)
     assert np.array_equal(ue2, ue2b)
 
 
@@ -162,7 +165,7 @@ def test_other_gaussian_radius_uses_tile_kernel():
     q = o.with_params(g_radius=3, sigma=2.0)
     ref = o.solve(phi, lam, "jacobi", q, steps=20)
     assert np.max(np.abs(u - ref.u)) <= U_TOL
-    assert d.dehaze_sweep_shape(ctx(), 41, 70, d.JACOBI) == (0, 0)  # R != 2: tile kernel, nothing tuned
+    assert d.dehaze_sweep_shape(ctx(), 41, 70, d.JACOBI) == (0, 0, 0)  # R != 2: tile kernel, nothing tuned
 
 
 def test_autotuned_shape_is_recorded():
@@ -170,7 +173,7 @@ def test_autotuned_shape_is_recorded():
     import paper_2506_08793_amd as d
     I, t32, A32, lam, phi = _inputs(200, 150, 65)
     u, st = _gpu_solve(I, t32, A32, scheme=1, max_outer=7, rel_tol=0.0)
-    k, srows = d.dehaze_sweep_shape(ctx(), 200, 150, d.JACOBI)
-    say(f"  autotuned K={k} S={srows}")
-    assert 1 <= k <= 4 and srows in (8, 12, 16, 20, 24, 28, 32, 40, 48, 64, 96, 128)
+    k, srows, cols = d.dehaze_sweep_shape(ctx(), 200, 150, d.JACOBI)
+    say(f"  autotuned K={k} S={srows} C={cols}")
+    assert 1 <= k <= 4 and 4 <= srows <= 131 and cols in (1, 2)
     assert np.max(np.abs(u - o.solve(phi, lam, "jacobi", steps=7).u)) <= U_TOL
