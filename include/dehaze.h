@@ -97,7 +97,11 @@ typedef struct dehaze_params {
   int32_t strip_rows;       /* output rows per wavefront of the register-resident sweep kernel; 0 = the
                                tuned value (every value gives bit-identical results) */
   int32_t lane_columns;     /* adjacent columns per lane of that kernel (1 or 2); 0 = tuned */
-  int32_t reserved[3];      /* must be zero */
+  int32_t stall_window;     /* lagged-diffusivity solves that start from a given iterate (u0 or the network):
+                               if over this many outer steps the lowest rho did not fall below 0.9 times
+                               its value at the window's start, the image restarts once from Phi
+                               (0 = never; default 64) */
+  int32_t reserved[2];      /* must be zero */
 } dehaze_params;
 
 typedef struct dehaze_stats {
@@ -109,13 +113,15 @@ typedef struct dehaze_stats {
   double  rel_residual0;    /* the same at the starting iterate */
   float   A[3];             /* atmospheric light used */
   int32_t status;           /* DEHAZE_OK, DEHAZE_ENOTCONV or DEHAZE_ENONFINITE for this image */
+  int32_t restarts;         /* 1 if the solve stalled from its given start and restarted from Phi */
+  int32_t reserved;
 } dehaze_stats;
 
 typedef struct dehaze_ctx dehaze_ctx;
 
 /* Fills *p with the defaults listed above (scheme = DEHAZE_PICARD_KRYLOV,
    max_outer = 5000, max_inner = 30, rel_tol = 1e-5, inner_rtol = 0.1,
-   check_every = 16, inner_refine = 0).  Returns DEHAZE_EINVAL for NULL. */
+   check_every = 16, inner_refine = 0, stall_window = 64).  Returns DEHAZE_EINVAL for NULL. */
 int dehaze_params_default(dehaze_params* p);
 
 /* sizeof(dehaze_params) and sizeof(dehaze_stats), so bindings can check their mirrors. */

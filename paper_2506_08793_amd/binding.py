@@ -33,7 +33,7 @@ class Params(ctypes.Structure):
         ("atm_divisor", c_int32), ("warm_start", c_int32), ("nonlocal_term", c_int32),
         ("adaptive", c_int32), ("edge_preserving", c_int32), ("sweeps_per_launch", c_int32),
         ("inner_refine", c_int32), ("strip_rows", c_int32), ("lane_columns", c_int32),
-        ("reserved", c_int32 * 3),
+        ("stall_window", c_int32), ("reserved", c_int32 * 2),
     ]
 
     def replace(self, **kw) -> "Params":
@@ -50,12 +50,14 @@ class Stats(ctypes.Structure):
     _fields_ = [
         ("outer", c_int32), ("converged", c_int32), ("inner", c_int64), ("applications", c_int64),
         ("rel_residual", c_double), ("rel_residual0", c_double), ("A", c_float * 3), ("status", c_int32),
+        ("restarts", c_int32), ("reserved", c_int32),
     ]
 
     def as_dict(self) -> dict:
         return {"outer": self.outer, "converged": bool(self.converged), "inner": self.inner,
                 "applications": self.applications, "rel_residual": self.rel_residual,
-                "rel_residual0": self.rel_residual0, "A": list(self.A), "status": self.status}
+                "rel_residual0": self.rel_residual0, "A": list(self.A), "status": self.status,
+                "restarts": self.restarts}
 
 
 class Image(ctypes.Structure):

@@ -53,6 +53,7 @@ int check_params(const dehaze_params* p) {
   if (p->inner_refine < 0) { set_error("inner_refine must be >= 0"); return DEHAZE_EINVAL; }
   if (p->strip_rows < 0) { set_error("strip_rows must be >= 0"); return DEHAZE_EINVAL; }
   if (p->lane_columns < 0 || p->lane_columns > 2) { set_error("lane_columns must be 0, 1 or 2"); return DEHAZE_EINVAL; }
+  if (p->stall_window < 0) { set_error("stall_window must be >= 0"); return DEHAZE_EINVAL; }
   for (int r : p->reserved)
     if (r != 0) { set_error("reserved fields of dehaze_params must be zero"); return DEHAZE_EINVAL; }
   if (!(p->inner_rtol > 0.0)) { set_error("inner_rtol must be positive"); return DEHAZE_EINVAL; }
@@ -118,6 +119,7 @@ int dehaze_params_default(dehaze_params* p) {
   p->sweeps_per_launch = 0;
   p->strip_rows = 0;
   p->lane_columns = 0;
+  p->stall_window = 64;
   return DEHAZE_OK;
 }
 

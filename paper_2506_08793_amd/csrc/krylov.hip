@@ -34,6 +34,7 @@ KConst make_kconst(const dehaze_params& p) {
   c.R = R;
   c.nonlocal_term = p.nonlocal_term;
   c.edge_preserving = p.edge_preserving;
+  c.stall_window = p.stall_window;
   return c;
 }
 
@@ -150,9 +151,10 @@ __global__ __launch_bounds__(NT) void k_tile_map(int* tile_img, int tile0, int n
 
 __global__ __launch_bounds__(NT) void k_set_desc(KImg* d, int i, KImg h) { d[i] = h; }
 
-__global__ __launch_bounds__(NT) void k_init_u(KImg I, const float* __restrict__ u0) {
+__global__ __launch_bounds__(NT) void k_init_u(KImg I, const float* __restrict__ u0, KScal* sc) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y;
+  if (x == 0 && y == 0) sc->warm = u0 ? 1 : 0;
   if (x >= I.W) return;
   const size_t plane = static_cast<size_t>(I.H) * I.P;
   for (int c = 0; c < 3; ++c) {
@@ -209,16 +211,29 @@ __global__ __launch_bounds__(NT) void k_res(const KImg* __restrict__ imgs, KScal
                                                       : 0.0;
   }
   double acc[3] = {0.0, 0.0, 0.0};  // ||r||^2 (float64), ||Phi||^2, ||r||^2 of the float32 copy
+  // a restart replaces the iterate by Phi: every tile of the image reads Phi
+  // in place of u (halo included) and writes it over its own part of u
+  const bool restart = !LINEAR && !final && sc->restart;
   for (int c = 0; c < 3; ++c) {
     const double* uc = I.u + c * plane;
     const double* unc = I.un + c * plane;
+    const float* pc = I.phi + c * plane;
     for (int i = tid; i < SY * SX; i += NT) {
       const int ly = i / SX, lx = i - (i / SX) * SX;
       const int yy = tp.y0 - HALO + ly, xx = tp.x0 - HALO + lx;
       const bool in = yy >= 0 && yy < I.H && xx >= 0 && xx < I.W;
       const size_t e = static_cast<size_t>(yy) * I.P + xx;
-      us[ly][lx] = in ? uc[e] : 0.0;
+      us[ly][lx] = in ? (restart ? static_cast<double>(pc[e]) : uc[e]) : 0.0;
       if (LINEAR) ud[ly][lx] = in ? unc[e] : 0.0;
+    }
+    if (restart) {
+      for (int k = 0; k < kPixPerThread; ++k) {
+        const int gy = tp.y0 + ty + 4 * k;
+        if (gx < I.W && gy < I.H) {
+          const size_t e = static_cast<size_t>(gy) * I.P + gx;
+          I.u[c * plane + e] = static_cast<double>(pc[e]);
+        }
+      }
     }
     __syncthreads();
     auto UD = [&](int y, int x) -> double { return LINEAR ? ud[y][x] : us[y][x]; };
@@ -308,6 +323,23 @@ __global__ __launch_bounds__(NT) void k_red_res(const KImg* __restrict__ imgs, K
     } else if (kc.rel_tol > 0.0 && rel <= kc.rel_tol) {
       sc->converged = 1;
     }
+    if (!final && !sc->converged) {
+      if (sc->res_evals == 1 || sc->restart) {  // a new start: open a window
+        sc->restart = 0;
+        sc->best = sc->mark = rel;
+        sc->since = 0;
+      } else if (kc.stall_window > 0) {
+        sc->best = fmin(sc->best, rel);
+        if (++sc->since >= kc.stall_window) {
+          if (sc->warm && !sc->restarted && !(sc->best < 0.9 * sc->mark)) {
+            sc->restart = 1;
+            sc->restarted = 1;
+          }
+          sc->mark = sc->best;
+          sc->since = 0;
+        }
+      }
+    }
   } else {
     sc->res_evals += 1;
   }
@@ -319,7 +351,9 @@ __global__ __launch_bounds__(NT) void k_red_res(const KImg* __restrict__ imgs, K
     sc->beta = 0.0;
     sc->half_done = 0;
     sc->pass_inner = 0;
-    sc->inner_done = (tot[2] > 0.0 && isfinite(tot[2])) ? 0 : 1;
+    // no inner solve on a step that decided a restart: the next residual
+    // pass replaces the iterate
+    sc->inner_done = (tot[2] > 0.0 && isfinite(tot[2]) && !sc->restart) ? 0 : 1;
   }
 }
 
@@ -642,7 +676,8 @@ int krylov_init(const KrylovBatch& b, const KImg* h_imgs, const float* const* u0
     hipLaunchKernelGGL(k_tile_map, dim3((m.ntiles + NT - 1) / NT), dim3(NT), 0, s,
                        const_cast<int*>(b.d_tile_img), m.tile0, m.ntiles, i);
     DZ_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_init_u, dim3((m.W + NT - 1) / NT, m.H), dim3(NT), 0, s, m, u0 ? u0[i] : nullptr);
+    hipLaunchKernelGGL(k_init_u, dim3((m.W + NT - 1) / NT, m.H), dim3(NT), 0, s, m, u0 ? u0[i] : nullptr,
+                       b.d_scal + i);
     DZ_CHECK_LAUNCH();
   }
   return DEHAZE_OK;

@@ -1,5 +1,12 @@
 // Lagged-diffusivity (Picard) solve of the main PDE over a list of images.
 //
+// A solve started from a given iterate (the caller's u0 or the network's
+// prediction) is watched: when over stall_window outer steps its lowest rho
+// has not fallen below 0.9 times the value at the window's start, it restarts
+// once from Phi.  The fixed point of the discretisation can stall from some
+// starting points (the tangential differences make the operator
+// nonsymmetric), while the start Phi is the one the plain method uses.
+//
 // Outer step n (for every image that has not converged):
 //   1. r_n = Phi - L_{D(u_n)} u_n, formed in float64 from the float64 iterate
 //      u_n; D(u_n) is stored per face (float32) for the inner solve, together
@@ -53,8 +60,13 @@ struct KScal {
   int outer;               // updates applied
   long long inner_total;
   long long res_evals;
-  unsigned reserved;
-  int pad[2];
+  // stall watch (solves started from a given iterate): lowest rho so far, its
+  // value at the start of the current window, steps into the window
+  double best, mark;
+  int since;
+  int warm;                // started from a given iterate
+  int restart;             // restart from Phi at the next residual pass
+  int restarted;           // restarted once already
 };
 
 struct KConst {
@@ -69,6 +81,7 @@ struct KConst {
   int R;
   int nonlocal_term;
   int edge_preserving;
+  int stall_window;        // 0: never restart
 };
 KConst make_kconst(const dehaze_params& p);
 

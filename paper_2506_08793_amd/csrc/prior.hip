@@ -155,6 +155,56 @@ __global__ __launch_bounds__(256) void k_colmin(const float* __restrict__ mrow, 
   }
 }
 
+// Column pass held in registers, for a compile-time patch.  A thread owns
+// one column and a segment of PATCH output rows starting at bs; the row
+// c = bs + r lies in every window [y - r, y + r] of the segment, so each
+// output is min(min(rows y - r .. c), min(rows c .. y + r)): one suffix and
+// one prefix scan over 4r + 1 rows, no shared memory and no barrier.
+template <int PATCH>
+__global__ __launch_bounds__(256) void k_colmin_reg(const float* __restrict__ mrow, float* __restrict__ m,
+                                                    float* __restrict__ dc, int H, int W, int P,
+                                                    float* __restrict__ dark, uint8_t* __restrict__ dark_u8) {
+  constexpr int r = PATCH / 2;
+  constexpr int NR = 4 * r + 1;  // rows bs - r .. bs + 3r
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= W) return;
+  const int bs = blockIdx.y * PATCH;
+  float dmin[PATCH];
+#pragma unroll
+  for (int i = 0; i < PATCH; ++i) dmin[i] = INFINITY;
+  for (int ch = 0; ch < 3; ++ch) {
+    const float* src = mrow + static_cast<size_t>(ch) * H * P + x;
+    float v[NR];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+      const int y = bs - r + i;
+      v[i] = (y >= 0 && y < H) ? src[static_cast<size_t>(y) * P] : INFINITY;
+    }
+    // v[i] <- min(v[i .. 2r]) below the split row, min(v[2r .. i]) above it
+#pragma unroll
+    for (int i = 2 * r - 1; i >= 0; --i) v[i] = fminf(v[i], v[i + 1]);
+#pragma unroll
+    for (int i = 2 * r + 1; i < NR; ++i) v[i] = fminf(v[i], v[i - 1]);
+    float* dst = m + static_cast<size_t>(ch) * H * P + x;
+#pragma unroll
+    for (int i = 0; i < PATCH; ++i) {
+      const int y = bs + i;
+      const float o = fminf(v[i], v[i + 2 * r]);
+      if (y < H) dst[static_cast<size_t>(y) * P] = o;
+      dmin[i] = fminf(dmin[i], o);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < PATCH; ++i) {
+    const int y = bs + i;
+    if (y < H) {
+      dc[static_cast<size_t>(y) * P + x] = dmin[i];
+      if (dark) dark[static_cast<size_t>(y) * W + x] = dmin[i];
+      if (dark_u8) dark_u8[static_cast<size_t>(y) * W + x] = static_cast<uint8_t>(rintf(dmin[i] * 255.0f));
+    }
+  }
+}
+
 // ------------------------------------------------------------ airlight
 // Order-preserving map of a float to uint32 (larger key <-> larger value);
 // -0 is folded onto +0 so that equal values have equal keys.
@@ -518,7 +568,11 @@ int launch_patch_min(const void* I, int dtype, int layout, int H, int W, int pit
                        pitch, patch, b.Ip, b.mrow, b.P);
     DZ_CHECK_LAUNCH();
   }
-  {
+  if (patch == 15) {
+    dim3 grid((W + 255) / 256, (H + 14) / 15);
+    hipLaunchKernelGGL(k_colmin_reg<15>, grid, dim3(256), 0, s, b.mrow, b.m, b.dc, H, W, b.P, dark, dark_u8);
+    DZ_CHECK_LAUNCH();
+  } else {
     const int Ly = (kColY + 2 * r + patch - 1) / patch * patch;
     dim3 grid((W + kColX - 1) / kColX, (H + kColY - 1) / kColY);
     hipLaunchKernelGGL(k_colmin, grid, dim3(256), 2 * Ly * kColX * sizeof(float), s, b.mrow, b.m,

@@ -215,6 +215,8 @@ int run_sweeps(Ctx& ctx, const SolveArgs& a, const dehaze_params& p, dehaze_stat
     st->applications = done;
     st->rel_residual = rho;
     st->rel_residual0 = rho0;
+    st->restarts = 0;
+    st->reserved = 0;
     DZ_HIP(hipMemcpyAsync(st->A, a.A, 3 * sizeof(float), hipMemcpyDeviceToHost, s));
     DZ_HIP(hipStreamSynchronize(s));
     st->status = status;
@@ -269,6 +271,8 @@ void fill_stats(const KScal& k, dehaze_stats* st) {
   st->rel_residual = k.rel;
   st->rel_residual0 = k.rel0;
   st->status = k.nonfinite ? DEHAZE_ENONFINITE : DEHAZE_OK;
+  st->restarts = k.restarted;
+  st->reserved = 0;
 }
 
 // One lagged-diffusivity step for every image still iterating.

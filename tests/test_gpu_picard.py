@@ -108,3 +108,49 @@ def test_picard_not_converged_status():
     u, st = _solve(I, t32, A32, max_outer=3, rel_tol=1e-12, check_every=1)
     assert not st["converged"] and st["status"] == -4 and st["outer"] == 3
     assert np.all(np.isfinite(u))
+
+
+def test_stalled_start_restarts_from_phi():
+    # A solve from a given iterate whose rho stops falling restarts from Phi:
+    # with a one-step window the first step that gains less than 10% triggers
+    # it, after which the iteration is the cold one step for step, so the
+    # converged result equals the cold solve bit for bit.
+    require_gpu()
+    I, t32, A32, lam, phi = _inputs(48, 40, 14, beta=1.0, occlusion=True)
+    rng = np.random.default_rng(5)
+    u0 = phi + rng.normal(0.0, 0.5, size=phi.shape)
+    say("picard restart from a given start (window 1)")
+    kw = dict(max_outer=3000, rel_tol=1e-5, check_every=16)
+    uc, stc = _solve(I, t32, A32, **kw)
+    uw, stw = _solve(I, t32, A32, u0=u0, stall_window=1, **kw)
+    say(f"  cold {stc}\n  restarted {stw}")
+    assert stc["converged"] and stc["restarts"] == 0
+    assert stw["converged"] and stw["restarts"] == 1
+    assert stw["outer"] > stc["outer"]
+    assert np.array_equal(uw, uc)
+    # with the watch switched off the same start is never restarted
+    un, stn = _solve(I, t32, A32, u0=u0, stall_window=0, **kw)
+    assert stn["restarts"] == 0
+
+
+def test_network_start_that_stalls_is_restarted():
+    # 512x512 window (seed 9103): from the trained network's prediction the
+    # lagged-diffusivity iteration levels off near rho = 3.7e-5 (exact
+    # sparse-LU steps of the oracle level off there too), while from Phi it
+    # converges; the stall watch restarts it and the solve converges.
+    require_gpu()
+    import paper_2506_08793_amd as d
+    from paper_2506_08793_amd import warmstart
+    warmstart.load(ctx(), warmstart.default_weights_path())
+    img = synth.hazy_window(512, 512, 9103)
+    I = dev(img["I"])
+    pr = d.dehaze_prior(ctx(), I, outputs=("t",))
+    say("picard 512x512 window 9103 warm vs cold")
+    pw = d.dehaze_params_default(max_outer=4000, rel_tol=1e-5, warm_start=1)
+    pc = d.dehaze_params_default(max_outer=4000, rel_tol=1e-5)
+    uw, stw = d.dehaze_solve(ctx(), I, pr["t"], pr["A"], params=pw)
+    uc, stc = d.dehaze_solve(ctx(), I, pr["t"], pr["A"], params=pc)
+    say(f"  warm {stw}\n  cold {stc}")
+    assert stc["converged"] and stw["converged"]
+    assert stw["restarts"] == 1
+    assert np.array_equal(host(uw), host(uc))
