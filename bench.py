@@ -47,7 +47,8 @@ HBM_PEAK_GBS = 8000.0
 # A different source hash reports null.
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 TRAFFIC_KIB = {
-    "0649ddcb7a47fd54": {"1x16": [23545.9, 12864.5], "1x32": [18153.1, 12864.0], "1x64": [15457.1, 12864.0], "1x128": [14109.1, 12864.0], "2x16": [27396.6, 12288.0], "2x32": [20445.6, 12288.0], "2x64": [16872.0, 12288.0], "2x128": [15063.8, 12288.0], "3x16": [26736.3, 12928.0], "3x32": [22281.8, 12928.0], "3x64": [18565.0, 12928.0], "3x128": [16218.4, 12928.0], "4x16": [45496.5, 12288.0], "4x32": [22730.8, 12288.0], "4x64": [20508.1, 12288.0], "4x128": [17841.1, 12288.0]},
+    # bench's own dispatches at K=3, S=20, C=1 (median of 264), shape pinned
+    "910fc2faecf34afb": {"3x20x1": [38943.2, 12928.6]},
 }
 
 
