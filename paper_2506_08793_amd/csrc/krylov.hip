@@ -10,6 +10,7 @@
 #include <cmath>
 
 #include "krylov.hpp"
+#include "wave.hpp"
 
 namespace dz {
 
@@ -39,6 +40,7 @@ KConst make_kconst(const dehaze_params& p) {
 }
 
 int krylov_tiles(int H, int W) { return ((W + kKTX - 1) / kKTX) * ((H + kKTY - 1) / kKTY); }
+int krylov_units(int H, int W) { return 3 * ((W + kUOW - 1) / kUOW) * ((H + kUS - 1) / kUS); }
 
 namespace {
 
@@ -47,7 +49,7 @@ struct KCarve {
   size_t bytes;
 };
 
-KCarve carve(void* base, int H, int W, int tile0) {
+KCarve carve(void* base, int H, int W, int tile0, int unit0) {
   KCarve k{};
   const int P = padded_pitch(W + 1);
   const size_t plane = static_cast<size_t>(H) * P;
@@ -60,6 +62,9 @@ KCarve carve(void* base, int H, int W, int tile0) {
   m.tiles_x = (W + kKTX - 1) / kKTX;
   m.ntiles = krylov_tiles(H, W);
   m.tile0 = tile0;
+  m.ucols = (W + kUOW - 1) / kUOW;
+  m.nunits = krylov_units(H, W);
+  m.unit0 = unit0;
   m.phi = cv.take<float>(3 * plane);
   m.lam = cv.take<float>(plane);
   m.u = cv.take<double>(3 * plane);
@@ -78,6 +83,13 @@ KCarve carve(void* base, int H, int W, int tile0) {
   m.x = cv.take<float>(3 * plane);
   k.bytes = cv.used();
   return k;
+}
+
+// One of a ping-pong pair, chosen without indexing the descriptor's array at
+// run time (a run-time index sends the whole descriptor to scratch memory).
+template <typename T>
+__device__ __forceinline__ T* pick(T* const (&pair)[2], int which) {
+  return which ? pair[1] : pair[0];
 }
 
 constexpr int NT = 256;
@@ -127,11 +139,12 @@ __device__ __forceinline__ void write_partials(double (&v)[N], double* part, int
 // fixed assignment to threads and a fixed tree; valid in thread 0.  Run by
 // the per-image reduction kernels (one workgroup per image) after the kernel
 // that wrote the partials, so plain loads see them.
-template <int N>
+template <int N, bool UNITS = false>
 __device__ __forceinline__ void image_sums(const KImg& I, const double* part, double (&tot)[N]) {
   for (int k = 0; k < N; ++k) tot[k] = 0.0;
-  for (int q = threadIdx.x; q < I.ntiles; q += NT)
-    for (int k = 0; k < N; ++k) tot[k] += part[static_cast<size_t>(I.tile0 + q) * kKPart + k];
+  const int n = UNITS ? I.nunits : I.ntiles, first = UNITS ? I.unit0 : I.tile0;
+  for (int q = threadIdx.x; q < n; q += NT)
+    for (int k = 0; k < N; ++k) tot[k] += part[static_cast<size_t>(first + q) * kKPart + k];
   block_sum<N>(tot);
 }
 
@@ -429,10 +442,10 @@ __global__ __launch_bounds__(NT) void k_bicg_a(const KImg* __restrict__ imgs, KS
   const float beta = first ? 0.0f : static_cast<float>(sc->beta);
   const float omega = static_cast<float>(sc->omega);
   const float* rs = first ? I.rhat : I.r;
-  const float* po = I.p[1 - par];
-  const float* vo = I.v[1 - par];
-  float* pn_out = I.p[par];
-  float* vn_out = I.v[par];
+  const float* po = pick(I.p, 1 - par);
+  const float* vo = pick(I.v, 1 - par);
+  float* pn_out = pick(I.p, par);
+  float* vn_out = pick(I.v, par);
   const int tid = threadIdx.x, tx = tid & (kKTX - 1), ty = tid / kKTX;
   const int gx = tp.x0 + tx;
   const size_t plane = static_cast<size_t>(I.H) * I.P;
@@ -472,13 +485,14 @@ __global__ __launch_bounds__(NT) void k_bicg_a(const KImg* __restrict__ imgs, KS
   write_partials<1>(acc, part, g);
 }
 
+template <bool UNITS>
 __global__ __launch_bounds__(NT) void k_red_a(const KImg* __restrict__ imgs, KScal* scal, const double* part) {
   const int im = blockIdx.x;
   const KImg I = imgs[im];
   KScal* sc = scal + im;
   if (sc->converged || sc->inner_done) return;
   double tot[1];
-  image_sums<1>(I, part, tot);
+  image_sums<1, UNITS>(I, part, tot);
   if (threadIdx.x != 0) return;
   const double sigma = tot[0];
   if (sigma == 0.0 || !isfinite(sigma)) sc->inner_done = 1;
@@ -502,7 +516,7 @@ __global__ __launch_bounds__(NT) void k_bicg_b(const KImg* __restrict__ imgs, KS
   const TilePos tp = tile_pos(I, im, g);
   const float alpha = static_cast<float>(sc->alpha);
   const float* rs = first ? I.rhat : I.r;
-  const float* vn = I.v[par];
+  const float* vn = pick(I.v, par);
   const int tid = threadIdx.x, tx = tid & (kKTX - 1), ty = tid / kKTX;
   const int gx = tp.x0 + tx;
   const size_t plane = static_cast<size_t>(I.H) * I.P;
@@ -545,6 +559,7 @@ __global__ __launch_bounds__(NT) void k_bicg_b(const KImg* __restrict__ imgs, KS
   write_partials<3>(acc, part, g);
 }
 
+template <bool UNITS>
 __global__ __launch_bounds__(NT) void k_red_b(const KImg* __restrict__ imgs, KScal* scal, const double* part,
                                                KConst kc) {
   const int im = blockIdx.x;
@@ -552,7 +567,7 @@ __global__ __launch_bounds__(NT) void k_red_b(const KImg* __restrict__ imgs, KSc
   KScal* sc = scal + im;
   if (sc->converged || sc->inner_done) return;
   double tot[3];
-  image_sums<3>(I, part, tot);
+  image_sums<3, UNITS>(I, part, tot);
   if (threadIdx.x != 0) return;
   if (!isfinite(tot[0]) || !isfinite(tot[1]) || !isfinite(tot[2])) {
     sc->inner_done = 1;
@@ -560,6 +575,148 @@ __global__ __launch_bounds__(NT) void k_red_b(const KImg* __restrict__ imgs, KSc
     if (tot[2] <= kc.eta * kc.eta * sc->bnorm2) sc->half_done = 1;
     sc->omega = tot[1] > 0.0 ? tot[0] / tot[1] : 0.0;
   }
+}
+
+// ------------------------------------------------------------ BiCGSTAB, strips
+// The operator kernels (a) and (b) for the radius-2 Gaussian as register-
+// resident strip walks: one wavefront per (image, channel, group of kUOW
+// columns, strip of kUS rows); lane = column with a 2-column halo on each
+// side, horizontal neighbours by DPP shifts, vertical ones in 4-row windows.
+// Step r of the walk forms f = M^-1 q at input row r (q = p in (a), s in (b))
+// and applies the operator at row j = r - 2.  Loads go through buffer
+// resources with scalar row offsets, three rows ahead into 4-slot rings.
+// MODE 0 is (a): p = r + beta (p - omega v); v = L M^-1 p; partial (rhat, v).
+// MODE 1 is (b): s = r - alpha v; t = L M^-1 s; partials (t, s), (t, t), (s, s).
+template <int MODE, bool FIRST>
+__global__ __launch_bounds__(256) void k_bicg_strip(const KImg* __restrict__ imgs, KScal* scal,
+                                                     const int* __restrict__ unit_img, double* upart, KConst kc,
+                                                     int par, int nunits) {
+#pragma clang fp contract(off)
+  constexpr int NA = MODE == 0 ? 2 : 1;  // partial sums
+  constexpr int RING = 4, AHEAD = 3;
+  const int gw = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (gw >= nunits) return;
+  // uniform per wavefront: keeps the descriptor and everything from it scalar
+  const int im = __builtin_amdgcn_readfirstlane(unit_img[gw]);
+  const KImg I = imgs[im];
+  const KScal* sc = scal + im;
+  if (sc->converged || sc->inner_done) return;  // uniform per wavefront
+  const int u = gw - I.unit0;
+  const int c = u % 3, rest = u / 3;
+  const int col = rest % I.ucols, strip = rest / I.ucols;
+  const int lane = threadIdx.x & 63;
+  const int x = col * kUOW - 2 + lane;
+  const bool xin = x >= 0 && x < I.W;
+  const unsigned long long live = __builtin_amdgcn_ballot_w64(xin);
+  const bool out_lane = lane >= 2 && lane < 2 + kUOW && xin;
+  const int y0 = strip * kUS, y1 = min(y0 + kUS, I.H);
+  const int H = I.H, P = I.P;
+  const unsigned pb = static_cast<unsigned>(H) * P * 4u, pby = static_cast<unsigned>(H + 1) * P * 4u;
+  const size_t plane = static_cast<size_t>(H) * P, plane_y = static_cast<size_t>(H + 1) * P;
+  const float* rsrc = FIRST ? I.rhat : I.r;
+  const __amdgpu_buffer_rsrc_t b_rs = plane_rsrc(rsrc + c * plane, pb);
+  const __amdgpu_buffer_rsrc_t b_id = plane_rsrc(I.invd + c * plane, pb);
+  const __amdgpu_buffer_rsrc_t b_dx = plane_rsrc(I.Dx + c * plane, pb);
+  const __amdgpu_buffer_rsrc_t b_dy = plane_rsrc(I.Dy + c * plane_y, pby);
+  const __amdgpu_buffer_rsrc_t b_la = plane_rsrc(I.lam, pb);
+  // (a): old p and v, rhat for the dot product; (b): v of this iteration
+  const __amdgpu_buffer_rsrc_t b_po = plane_rsrc(MODE == 0 ? pick(I.p, 1 - par) + c * plane : pick(I.v, par) + c * plane, pb);
+  const __amdgpu_buffer_rsrc_t b_vo = plane_rsrc(pick(I.v, 1 - par) + c * plane, pb);
+  const __amdgpu_buffer_rsrc_t b_rh = plane_rsrc(I.rhat + c * plane, pb);
+  const __amdgpu_buffer_rsrc_t b_qo = plane_rsrc(MODE == 0 ? pick(I.p, par) + c * plane : I.s + c * plane, pb);
+  const __amdgpu_buffer_rsrc_t b_lo = plane_rsrc(MODE == 0 ? pick(I.v, par) + c * plane : I.t + c * plane, pb);
+  const int vx = min(max(x, 0), I.W - 1) * 4;   // cell columns
+  const int vf = min(max(x, 0), I.W) * 4;       // x-face columns (W + 1 faces)
+  const float beta = FIRST ? 0.0f : static_cast<float>(sc->beta);
+  const float omega = static_cast<float>(sc->omega);
+  const float alpha = static_cast<float>(sc->alpha);
+  const bool nl = kc.nonlocal_term != 0;
+  const float w0 = nl ? kc.w[2] : 0.0f, w1 = nl ? kc.w[1] : 0.0f, w2 = nl ? kc.w[0] : 0.0f;
+
+  auto soff = [&](int row) { return min(max(row, 0), H - 1) * P * 4; };
+  auto ld = [&](__amdgpu_buffer_rsrc_t b, int vo, int so) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(b, vo, so, 0));
+  };
+  // ring slots: inputs of row r (rs, the old p or v, old v, invd) and the
+  // operator's data of row r - 2 (Dx, Dy above and below, lambda, rhat)
+  float q_rs[RING], q_po[RING], q_vo[RING], q_id[RING];
+  float q_dx[RING], q_dya[RING], q_dyb[RING], q_la[RING], q_rh[RING];
+  auto issue = [&](int slot, int r) {
+    const int so = soff(r);
+    q_rs[slot] = ld(b_rs, vx, so);
+    if (MODE == 1 || !FIRST) q_po[slot] = ld(b_po, vx, so);
+    if (MODE == 0 && !FIRST) q_vo[slot] = ld(b_vo, vx, so);
+    q_id[slot] = ld(b_id, vx, so);
+    const int j = r - 2, sj = soff(j);
+    q_dx[slot] = ld(b_dx, vf, sj);
+    q_dya[slot] = ld(b_dy, vx, min(max(j, 0), H) * P * 4);
+    q_dyb[slot] = ld(b_dy, vx, min(max(j + 1, 0), H) * P * 4);
+    q_la[slot] = ld(b_la, vx, sj);
+    if (MODE == 0) q_rh[slot] = ld(b_rh, vx, sj);
+  };
+  float F[4] = {0.0f, 0.0f, 0.0f, 0.0f}, GH[4] = {0.0f, 0.0f, 0.0f, 0.0f}, Q[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  double acc[3] = {0.0, 0.0, 0.0};
+  const int rs0 = y0 - 2;
+#pragma unroll
+  for (int q = 0; q < AHEAD; ++q) issue(q, rs0 + q);
+
+  // step r: slot q holds row r's inputs and row r - 2's operator data
+  auto step = [&](int r, int q, bool out) __attribute__((always_inline)) {
+    const float rv = q_rs[q], idv = q_id[q];
+    float qv;
+    if (MODE == 0) qv = FIRST ? rv : rv + beta * (q_po[q] - omega * q_vo[q]);
+    else qv = rv - alpha * q_po[q];
+    const bool rin = r >= 0 && r < H;
+    const float f = keep_lanes(idv * qv, rin ? live : 0ull);
+    const float dx = q_dx[q], dya = q_dya[q], dyb = q_dyb[q], la = q_la[q], rh = q_rh[q];
+    issue((q + AHEAD) % RING, r + AHEAD);
+    if (rin && r >= y0 && r < y1 && out_lane)
+      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, qv), b_qo, vx, r * P * 4, 0);
+    const float fl1 = from_left(f), fr1 = from_right(f);
+    const float fl2 = from_left(fl1), fr2 = from_right(fr1);
+    const float ghn = __builtin_fmaf(w2, fl2 + fr2, __builtin_fmaf(w1, fl1 + fr1, w0 * f));
+    if (out) {
+      const int j = r - 2;
+      const float up = F[1], f0 = F[2], dn = F[3];
+      const float G = __builtin_fmaf(w2, GH[0] + ghn, __builtin_fmaf(w1, GH[1] + GH[3], w0 * GH[2]));
+      const float dxr = from_right(dx);
+      const float div = (dxr * (from_right(f0) - f0) - dx * (f0 - from_left(f0))) + (dyb * (dn - f0) - dya * (f0 - up));
+      const float lv = __builtin_fmaf(la, G, -div);
+      if (j < y1 && out_lane) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, lv), b_lo, vx, j * P * 4, 0);
+        if (MODE == 0) {
+          acc[0] += static_cast<double>(rh) * lv;
+        } else {
+          const float se = Q[2];
+          acc[0] += static_cast<double>(lv) * se;
+          acc[1] += static_cast<double>(lv) * lv;
+          acc[2] += static_cast<double>(se) * se;
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      F[i] = F[i + 1];
+      GH[i] = GH[i + 1];
+      Q[i] = Q[i + 1];
+    }
+    F[3] = f;
+    GH[3] = ghn;
+    Q[3] = qv;
+  };
+  // head: rows y0 - 2 .. y0 + 1 fill the windows; then rows j = y0 .. y1 - 1
+  int r = rs0;
+#pragma unroll
+  for (int q = 0; q < RING; ++q) step(r + q, q, false);
+  r += RING;
+  for (; r - 2 < y1; r += RING) {
+#pragma unroll
+    for (int q = 0; q < RING; ++q) step(r + q, q, true);
+  }
+  for (int k = 0; k < (MODE == 0 ? 1 : 3); ++k) acc[k] = wave_sum(acc[k]);
+  if (lane == 0)
+    for (int k = 0; k < (MODE == 0 ? 1 : 3); ++k) upart[static_cast<size_t>(gw) * kKPart + k] = acc[k];
+  (void)NA;
 }
 
 // (c) x += alpha M^-1 p + omega M^-1 s; r = s - omega t; rho = (rhat, r); beta.
@@ -575,7 +732,7 @@ __global__ __launch_bounds__(NT) void k_bicg_c(const KImg* __restrict__ imgs, KS
   const float alpha = static_cast<float>(sc->alpha);
   const float omega = static_cast<float>(sc->omega);
   const int half = sc->half_done;
-  const float* pn = I.p[par];
+  const float* pn = pick(I.p, par);
   const int tid = threadIdx.x, tx = tid & (kKTX - 1), ty = tid / kKTX;
   const int gx = tp.x0 + tx;
   const size_t plane = static_cast<size_t>(I.H) * I.P;
@@ -662,9 +819,9 @@ __global__ __launch_bounds__(NT) void k_update(const KImg* __restrict__ imgs, co
 
 }  // namespace
 
-size_t krylov_image_bytes(int H, int W) { return carve(nullptr, H, W, 0).bytes; }
+size_t krylov_image_bytes(int H, int W) { return carve(nullptr, H, W, 0, 0).bytes; }
 
-KImg krylov_carve(void* base, int H, int W, int tile0) { return carve(base, H, W, tile0).img; }
+KImg krylov_carve(void* base, int H, int W, int tile0, int unit0) { return carve(base, H, W, tile0, unit0).img; }
 
 int krylov_init(const KrylovBatch& b, const KImg* h_imgs, const float* const* u0, hipStream_t s) {
   hipLaunchKernelGGL(k_scal_reset, dim3((b.nimg + NT - 1) / NT), dim3(NT), 0, s, b.d_scal, b.nimg);
@@ -676,6 +833,11 @@ int krylov_init(const KrylovBatch& b, const KImg* h_imgs, const float* const* u0
     hipLaunchKernelGGL(k_tile_map, dim3((m.ntiles + NT - 1) / NT), dim3(NT), 0, s,
                        const_cast<int*>(b.d_tile_img), m.tile0, m.ntiles, i);
     DZ_CHECK_LAUNCH();
+    if (b.d_unit_img) {
+      hipLaunchKernelGGL(k_tile_map, dim3((m.nunits + NT - 1) / NT), dim3(NT), 0, s,
+                         const_cast<int*>(b.d_unit_img), m.unit0, m.nunits, i);
+      DZ_CHECK_LAUNCH();
+    }
     hipLaunchKernelGGL(k_init_u, dim3((m.W + NT - 1) / NT, m.H), dim3(NT), 0, s, m, u0 ? u0[i] : nullptr,
                        b.d_scal + i);
     DZ_CHECK_LAUNCH();
@@ -714,20 +876,42 @@ int krylov_snapshot(const KrylovBatch& b, hipStream_t s) {
 int krylov_inner(const KrylovBatch& b, const KConst& c, int it, hipStream_t s) {
   const int first = it == 1 ? 1 : 0;
   const int par = it & 1;
+  if (c.R == 2 && b.nunits > 0) {
+    const dim3 ug((b.nunits + 3) / 4);
+    if (first)
+      hipLaunchKernelGGL((k_bicg_strip<0, true>), ug, dim3(256), 0, s, b.d_imgs, b.d_scal, b.d_unit_img, b.d_upart,
+                         c, par, b.nunits);
+    else
+      hipLaunchKernelGGL((k_bicg_strip<0, false>), ug, dim3(256), 0, s, b.d_imgs, b.d_scal, b.d_unit_img, b.d_upart,
+                         c, par, b.nunits);
+    DZ_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_red_a<true>, dim3(b.nimg), dim3(NT), 0, s, b.d_imgs, b.d_scal, b.d_upart);
+    DZ_CHECK_LAUNCH();
+    if (first)
+      hipLaunchKernelGGL((k_bicg_strip<1, true>), ug, dim3(256), 0, s, b.d_imgs, b.d_scal, b.d_unit_img, b.d_upart,
+                         c, par, b.nunits);
+    else
+      hipLaunchKernelGGL((k_bicg_strip<1, false>), ug, dim3(256), 0, s, b.d_imgs, b.d_scal, b.d_unit_img, b.d_upart,
+                         c, par, b.nunits);
+    DZ_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_red_b<true>, dim3(b.nimg), dim3(NT), 0, s, b.d_imgs, b.d_scal, b.d_upart, c);
+    DZ_CHECK_LAUNCH();
+  } else {
 #define L_A(R) hipLaunchKernelGGL((k_bicg_a<R>), dim3(b.ntiles), dim3(NT), 0, s, b.d_imgs, b.d_scal, b.d_tile_img, \
                                   b.d_part, c, first, par)
 #define L_B(R) hipLaunchKernelGGL((k_bicg_b<R>), dim3(b.ntiles), dim3(NT), 0, s, b.d_imgs, b.d_scal, b.d_tile_img, \
                                   b.d_part, c, first, par)
-  DZ_KRYLOV_DISPATCH(c.R, L_A)
-  DZ_CHECK_LAUNCH();
-  hipLaunchKernelGGL(k_red_a, dim3(b.nimg), dim3(NT), 0, s, b.d_imgs, b.d_scal, b.d_part);
-  DZ_CHECK_LAUNCH();
-  DZ_KRYLOV_DISPATCH(c.R, L_B)
-  DZ_CHECK_LAUNCH();
-  hipLaunchKernelGGL(k_red_b, dim3(b.nimg), dim3(NT), 0, s, b.d_imgs, b.d_scal, b.d_part, c);
-  DZ_CHECK_LAUNCH();
+    DZ_KRYLOV_DISPATCH(c.R, L_A)
+    DZ_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_red_a<false>, dim3(b.nimg), dim3(NT), 0, s, b.d_imgs, b.d_scal, b.d_part);
+    DZ_CHECK_LAUNCH();
+    DZ_KRYLOV_DISPATCH(c.R, L_B)
+    DZ_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_red_b<false>, dim3(b.nimg), dim3(NT), 0, s, b.d_imgs, b.d_scal, b.d_part, c);
+    DZ_CHECK_LAUNCH();
 #undef L_A
 #undef L_B
+  }
   hipLaunchKernelGGL(k_bicg_c, dim3(b.ntiles), dim3(NT), 0, s, b.d_imgs, b.d_scal, b.d_tile_img, b.d_part, c, first,
                      par);
   DZ_CHECK_LAUNCH();

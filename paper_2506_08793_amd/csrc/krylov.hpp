@@ -28,9 +28,15 @@ constexpr int kKTX = 64;   // tile width of the Krylov kernels
 constexpr int kKTY = 16;   // tile height
 constexpr int kKPart = 4;  // doubles of partial sums per tile
 
+// Strip wavefronts of the BiCGSTAB operator kernels (Gaussian radius 2): one
+// wavefront per (channel, group of kUOW columns, strip of kUS rows).
+constexpr int kUS = 32;
+constexpr int kUOW = 60;
+
 struct KImg {
   int H, W, P;             // P: pitch of every plane, >= W + 1
   int tiles_x, ntiles, tile0;
+  int ucols, nunits, unit0; // strip wavefronts: column groups, count, first global index
   const float* phi;        // 3 planes
   const float* lam;        // 1 plane
   double* u;               // 3 planes, the iterate
@@ -88,10 +94,11 @@ KConst make_kconst(const dehaze_params& p);
 // Bytes of one image's planes (internal pitch) and its tile count.
 size_t krylov_image_bytes(int H, int W);
 int krylov_tiles(int H, int W);
+int krylov_units(int H, int W);
 // Fills a descriptor whose planes live at `base` (krylov_image_bytes bytes,
 // 256-byte aligned); phi/lam are carved here too and returned through the
 // descriptor (the front end writes them).
-KImg krylov_carve(void* base, int H, int W, int tile0);
+KImg krylov_carve(void* base, int H, int W, int tile0, int unit0);
 
 struct KrylovBatch {
   const KImg* d_imgs;      // device copy of the descriptors
@@ -100,6 +107,9 @@ struct KrylovBatch {
   double* d_part;          // kKPart doubles per tile
   int nimg;
   int ntiles;
+  const int* d_unit_img;   // image index of every strip wavefront
+  double* d_upart;         // kKPart doubles per strip wavefront
+  int nunits;
 };
 
 // Starting iterate: u = u0 (float, dense pitch W) or Phi; resets the scalars.

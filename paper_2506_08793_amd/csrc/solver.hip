@@ -233,6 +233,8 @@ struct KrylovPlan {
   KScal* d_scal = nullptr;
   int* d_tile_img = nullptr;
   double* d_part = nullptr;
+  int* d_unit_img = nullptr;
+  double* d_upart = nullptr;
   float* u0w = nullptr;   // network prediction (warm start), planar pitch W
   char* cnn_ws = nullptr;
   size_t bytes = 0;
@@ -242,13 +244,16 @@ KrylovPlan plan_krylov(void* ws, int H, int W, bool warm) {
   KrylovPlan pl;
   Carver cv(ws, ~size_t(0));
   char* arena = cv.take<char>(krylov_image_bytes(H, W));
-  pl.img = krylov_carve(arena, H, W, 0);
+  pl.img = krylov_carve(arena, H, W, 0, 0);
   const int nt = krylov_tiles(H, W);
+  const int nu = krylov_units(H, W);
   pl.Ip = cv.take<float>(3 * static_cast<size_t>(H) * pl.img.P);
   pl.d_imgs = cv.take<KImg>(1);
   pl.d_scal = cv.take<KScal>(1);
   pl.d_tile_img = cv.take<int>(nt);
   pl.d_part = cv.take<double>(static_cast<size_t>(kKPart) * nt);
+  pl.d_unit_img = cv.take<int>(nu);
+  pl.d_upart = cv.take<double>(static_cast<size_t>(kKPart) * nu);
   if (warm) {
     pl.u0w = cv.take<float>(3 * static_cast<size_t>(H) * W);
     pl.cnn_ws = cv.take<char>(cnn_forward_bytes(1, H, W));
@@ -305,7 +310,8 @@ namespace {
 
 bool same_key(const GraphCache& g, const KrylovBatch& b, const KConst& kc, int steps, const dehaze_params& p) {
   return g.exec && g.b.d_imgs == b.d_imgs && g.b.d_scal == b.d_scal && g.b.d_tile_img == b.d_tile_img &&
-         g.b.d_part == b.d_part && g.b.nimg == b.nimg && g.b.ntiles == b.ntiles && g.steps == steps &&
+         g.b.d_part == b.d_part && g.b.nimg == b.nimg && g.b.ntiles == b.ntiles &&
+         g.b.d_unit_img == b.d_unit_img && g.b.d_upart == b.d_upart && g.b.nunits == b.nunits && g.steps == steps &&
          g.max_inner == p.max_inner && g.refine == p.inner_refine && std::memcmp(&g.kc, &kc, sizeof(kc)) == 0;
 }
 
@@ -397,7 +403,8 @@ int run_krylov(Ctx& ctx, const SolveArgs& a, const dehaze_params& p, dehaze_stat
   if ((rc = launch_to_planar(a.I, a.dtype, a.layout, H, W, a.pitch, pl.Ip, P, s))) return rc;
   FusedOut fo{nullptr, nullptr, const_cast<float*>(pl.img.lam), const_cast<float*>(pl.img.phi), P, P};
   if ((rc = launch_prior_fused(nullptr, pl.Ip, P, a.t, W, a.A, H, W, p, fo, s))) return rc;
-  KrylovBatch b{pl.d_imgs, pl.d_scal, pl.d_tile_img, pl.d_part, 1, pl.img.ntiles};
+  KrylovBatch b{pl.d_imgs, pl.d_scal, pl.d_tile_img, pl.d_part, 1, pl.img.ntiles,
+                pl.d_unit_img, pl.d_upart, pl.img.nunits};
   const float* u0 = a.u0;
   if (p.warm_start) {
     const size_t plane = static_cast<size_t>(H) * P;
@@ -434,9 +441,12 @@ struct BatchPlan {
   KScal* d_scal = nullptr;
   int* d_tile_img = nullptr;
   double* d_part = nullptr;
+  int* d_unit_img = nullptr;
+  double* d_upart = nullptr;
   std::vector<float*> u0w;  // network predictions (warm start)
   char* cnn_ws = nullptr;
   int ntiles = 0;
+  int nunits = 0;
   size_t bytes = 0;
 };
 
@@ -451,11 +461,12 @@ BatchPlan plan_batch(void* ws, int n, const dehaze_image* im, bool warm) {
   }
   pl.prior_ws = cv.take<char>(prior_max);
   if (warm) pl.cnn_ws = cv.take<char>(cnn_max);
-  int tile0 = 0;
+  int tile0 = 0, unit0 = 0;
   for (int i = 0; i < n; ++i) {
     char* arena = cv.take<char>(krylov_image_bytes(im[i].H, im[i].W));
-    pl.imgs.push_back(krylov_carve(arena, im[i].H, im[i].W, tile0));
+    pl.imgs.push_back(krylov_carve(arena, im[i].H, im[i].W, tile0, unit0));
     tile0 += pl.imgs.back().ntiles;
+    unit0 += pl.imgs.back().nunits;
     const bool need_t = !im[i].t && !im[i].t_out;
     const bool need_A = !im[i].A && !im[i].A_out;
     pl.t_int.push_back(need_t ? cv.take<float>(static_cast<size_t>(im[i].H) * im[i].W) : nullptr);
@@ -463,10 +474,13 @@ BatchPlan plan_batch(void* ws, int n, const dehaze_image* im, bool warm) {
     pl.u0w.push_back(warm ? cv.take<float>(3 * static_cast<size_t>(im[i].H) * im[i].W) : nullptr);
   }
   pl.ntiles = tile0;
+  pl.nunits = unit0;
   pl.d_imgs = cv.take<KImg>(n);
   pl.d_scal = cv.take<KScal>(n);
   pl.d_tile_img = cv.take<int>(tile0);
   pl.d_part = cv.take<double>(static_cast<size_t>(kKPart) * tile0);
+  pl.d_unit_img = cv.take<int>(unit0);
+  pl.d_upart = cv.take<double>(static_cast<size_t>(kKPart) * unit0);
   pl.bytes = cv.used();
   return pl;
 }
@@ -561,7 +575,7 @@ int solve_batch(Ctx& ctx, int n, const dehaze_image* im, int dtype, int layout, 
     if ((rc = batch_front_end(ctx, pl, i, im[i], dtype, layout, p, &A_used[i], s))) return rc;
     u0[i] = p.warm_start ? pl.u0w[i] : im[i].u0;
   }
-  KrylovBatch b{pl.d_imgs, pl.d_scal, pl.d_tile_img, pl.d_part, n, pl.ntiles};
+  KrylovBatch b{pl.d_imgs, pl.d_scal, pl.d_tile_img, pl.d_part, n, pl.ntiles, pl.d_unit_img, pl.d_upart, pl.nunits};
   if ((rc = krylov_init(b, pl.imgs.data(), u0.data(), s))) return rc;
   std::vector<KScal> hs(n);
   if ((rc = krylov_loop(ctx, b, p, hs.data(), st != nullptr, s))) return rc;

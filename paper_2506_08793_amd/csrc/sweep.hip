@@ -20,6 +20,7 @@
 #include <utility>
 
 #include "internal.hpp"
+#include "wave.hpp"
 
 namespace dz {
 
@@ -239,30 +240,6 @@ int launch_sweep_r(int mode, const float* uin, float* uout, const float* phi, co
 // kernel and every fused multiply-add is explicit, so an output value is
 // computed by the same operation sequence whatever K and S are: the results
 // do not depend on the launch shape the tuner picks.
-
-// lane i <- lane i - 1 (column x - 1); lane 0 receives 0 (bound_ctrl)
-__device__ __forceinline__ float from_left(float v) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x138, 0xF, 0xF, true));
-}
-// lane i <- lane i + 1 (column x + 1); lane 63 receives 0 (bound_ctrl)
-__device__ __forceinline__ float from_right(float v) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x130, 0xF, 0xF, true));
-}
-
-// Buffer resource of one plane: the row offset then travels in a scalar
-// register and the lane's column offset is fixed, so no per-load address
-// arithmetic is left in the vector ALU.  Word 3 is the gfx9-family default
-// (32-bit dwords, no swizzle).
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const float* base, unsigned bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), 0, static_cast<int>(bytes), 0x00020000);
-}
-
-// out where the lane's bit of `live` is set, else 0 (one v_cndmask)
-__device__ __forceinline__ float keep_lanes(float out, unsigned long long live) {
-  float r;
-  asm volatile("v_cndmask_b32 %0, 0, %1, %2" : "=v"(r) : "v"(out), "s"(live));
-  return r;
-}
 
 // Register state of one sweep level, per column c of the lane: windows over
 // the last four rows it received (rows j-2 .. j+1 when it is about to
