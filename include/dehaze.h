@@ -97,10 +97,11 @@ typedef struct dehaze_params {
   int32_t strip_rows;       /* output rows per wavefront of the register-resident sweep kernel; 0 = the
                                tuned value (every value gives bit-identical results) */
   int32_t lane_columns;     /* adjacent columns per lane of that kernel (1 or 2); 0 = tuned */
-  int32_t stall_window;     /* lagged-diffusivity solves that start from a given iterate (u0 or the network):
-                               if over this many outer steps the lowest rho did not fall below 0.9 times
-                               its value at the window's start, the image restarts once from Phi
-                               (0 = never; default 64) */
+  int32_t stall_window;     /* lagged-diffusivity solves: if over this many outer steps the lowest rho did
+                               not fall below half its value at the window's start, an image that
+                               started from a given iterate (u0 or the network) restarts once from Phi;
+                               otherwise, when rel_tol > 0, its solve stops there (DEHAZE_ENOTCONV,
+                               stats.stalled = 1).  0 = never; default 256 */
   int32_t reserved[2];      /* must be zero */
 } dehaze_params;
 
@@ -114,14 +115,14 @@ typedef struct dehaze_stats {
   float   A[3];             /* atmospheric light used */
   int32_t status;           /* DEHAZE_OK, DEHAZE_ENOTCONV or DEHAZE_ENONFINITE for this image */
   int32_t restarts;         /* 1 if the solve stalled from its given start and restarted from Phi */
-  int32_t reserved;
+  int32_t stalled;          /* 1 if the solve stopped early because rho stopped falling */
 } dehaze_stats;
 
 typedef struct dehaze_ctx dehaze_ctx;
 
 /* Fills *p with the defaults listed above (scheme = DEHAZE_PICARD_KRYLOV,
    max_outer = 5000, max_inner = 30, rel_tol = 1e-5, inner_rtol = 0.1,
-   check_every = 16, inner_refine = 0, stall_window = 64).  Returns DEHAZE_EINVAL for NULL. */
+   check_every = 16, inner_refine = 0, stall_window = 256).  Returns DEHAZE_EINVAL for NULL. */
 int dehaze_params_default(dehaze_params* p);
 
 /* sizeof(dehaze_params) and sizeof(dehaze_stats), so bindings can check their mirrors. */

@@ -119,7 +119,7 @@ int dehaze_params_default(dehaze_params* p) {
   p->sweeps_per_launch = 0;
   p->strip_rows = 0;
   p->lane_columns = 0;
-  p->stall_window = 64;
+  p->stall_window = 256;
   return DEHAZE_OK;
 }
 

@@ -344,9 +344,14 @@ __global__ __launch_bounds__(NT) void k_red_res(const KImg* __restrict__ imgs, K
       } else if (kc.stall_window > 0) {
         sc->best = fmin(sc->best, rel);
         if (++sc->since >= kc.stall_window) {
-          if (sc->warm && !sc->restarted && !(sc->best < 0.9 * sc->mark)) {
-            sc->restart = 1;
-            sc->restarted = 1;
+          if (!(sc->best < 0.5 * sc->mark)) {
+            if (sc->warm && !sc->restarted) {
+              sc->restart = 1;
+              sc->restarted = 1;
+            } else if (kc.rel_tol > 0.0) {
+              sc->stalled = 1;
+              sc->converged = 1;  // done iterating; reported as not converged
+            }
           }
           sc->mark = sc->best;
           sc->since = 0;

@@ -1,11 +1,13 @@
 // Lagged-diffusivity (Picard) solve of the main PDE over a list of images.
 //
-// A solve started from a given iterate (the caller's u0 or the network's
-// prediction) is watched: when over stall_window outer steps its lowest rho
-// has not fallen below 0.9 times the value at the window's start, it restarts
-// once from Phi.  The fixed point of the discretisation can stall from some
-// starting points (the tangential differences make the operator
-// nonsymmetric), while the start Phi is the one the plain method uses.
+// Every solve is watched: when over stall_window outer steps its lowest rho
+// has not fallen below half its value at the window's start, an image
+// started from a given iterate (the caller's u0 or the network's prediction)
+// restarts once from Phi; any other image of a tolerance-terminated solve
+// stops there, reported as stalled.  The fixed-point iteration of this
+// discretisation can level off short of the tolerance (the tangential
+// differences make the operator nonsymmetric), and from some starting points
+// more than from Phi, the start the plain method uses.
 //
 // Outer step n (for every image that has not converged):
 //   1. r_n = Phi - L_{D(u_n)} u_n, formed in float64 from the float64 iterate
@@ -73,6 +75,7 @@ struct KScal {
   int warm;                // started from a given iterate
   int restart;             // restart from Phi at the next residual pass
   int restarted;           // restarted once already
+  int stalled;             // stopped: rho stopped falling (tolerance-terminated solves)
 };
 
 struct KConst {

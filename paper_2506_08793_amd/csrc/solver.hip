@@ -216,7 +216,7 @@ int run_sweeps(Ctx& ctx, const SolveArgs& a, const dehaze_params& p, dehaze_stat
     st->rel_residual = rho;
     st->rel_residual0 = rho0;
     st->restarts = 0;
-    st->reserved = 0;
+    st->stalled = 0;
     DZ_HIP(hipMemcpyAsync(st->A, a.A, 3 * sizeof(float), hipMemcpyDeviceToHost, s));
     DZ_HIP(hipStreamSynchronize(s));
     st->status = status;
@@ -270,14 +270,14 @@ int read_scalars(const KrylovBatch& b, KScal* h, hipStream_t s) {
 
 void fill_stats(const KScal& k, dehaze_stats* st) {
   st->outer = k.outer;
-  st->converged = (k.converged && !k.nonfinite) ? 1 : 0;
+  st->converged = (k.converged && !k.nonfinite && !k.stalled) ? 1 : 0;
   st->inner = k.inner_total;
   st->applications = 2 * k.inner_total + k.res_evals;
   st->rel_residual = k.rel;
   st->rel_residual0 = k.rel0;
   st->status = k.nonfinite ? DEHAZE_ENONFINITE : DEHAZE_OK;
   st->restarts = k.restarted;
-  st->reserved = 0;
+  st->stalled = k.stalled;
 }
 
 // One lagged-diffusivity step for every image still iterating.
@@ -391,7 +391,7 @@ int krylov_loop(Ctx& ctx, const KrylovBatch& b, const dehaze_params& p, KScal* h
 
 int image_status(const KScal& k, const dehaze_params& p) {
   if (k.nonfinite) return DEHAZE_ENONFINITE;
-  if (p.rel_tol > 0.0 && !k.converged) return DEHAZE_ENOTCONV;
+  if (p.rel_tol > 0.0 && (!k.converged || k.stalled)) return DEHAZE_ENOTCONV;
   return DEHAZE_OK;
 }
 
@@ -427,7 +427,8 @@ int run_krylov(Ctx& ctx, const SolveArgs& a, const dehaze_params& p, dehaze_stat
   }
   if (status == DEHAZE_ENONFINITE) set_error("residual is not finite");
   else if (status == DEHAZE_ENOTCONV)
-    set_error("rel_tol %g not reached in %d outer steps (rho %g)", p.rel_tol, hs.outer, hs.rel);
+    set_error("rel_tol %g not reached in %d outer steps (rho %g%s)", p.rel_tol, hs.outer, hs.rel,
+              hs.stalled ? ", stopped: rho stopped falling" : "");
   return status;
 }
 
