@@ -102,7 +102,13 @@ typedef struct dehaze_params {
                                started from a given iterate (u0 or the network) restarts once from Phi;
                                otherwise, when rel_tol > 0, its solve stops there (DEHAZE_ENOTCONV,
                                stats.stalled = 1).  0 = never; default 256 */
-  int32_t reserved[2];      /* must be zero */
+  int32_t guided_radius;    /* > 0: refine the estimated t with a guided filter (guide: channel mean of I,
+                               window (2r+1)^2 clipped to the image, He-Sun-Tang).  Table II ablates a
+                               guided filter without defining it; 0 (default) = the printed method */
+  int32_t dark_scales;      /* t_d averaged over patch sides ((patch - 1) >> k) | 1, k < dark_scales: a
+                               reading of the multiscale dark channel Table II ablates; 1 (default) = off */
+  double  guided_eps;       /* guided-filter regulariser (default 1e-3) */
+  int32_t reserved[4];      /* must be zero */
 } dehaze_params;
 
 typedef struct dehaze_stats {

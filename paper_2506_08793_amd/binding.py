@@ -33,7 +33,8 @@ class Params(ctypes.Structure):
         ("atm_divisor", c_int32), ("warm_start", c_int32), ("nonlocal_term", c_int32),
         ("adaptive", c_int32), ("edge_preserving", c_int32), ("sweeps_per_launch", c_int32),
         ("inner_refine", c_int32), ("strip_rows", c_int32), ("lane_columns", c_int32),
-        ("stall_window", c_int32), ("reserved", c_int32 * 2),
+        ("stall_window", c_int32), ("guided_radius", c_int32), ("dark_scales", c_int32),
+        ("guided_eps", c_double), ("reserved", c_int32 * 4),
     ]
 
     def replace(self, **kw) -> "Params":

@@ -54,6 +54,15 @@ int check_params(const dehaze_params* p) {
   if (p->strip_rows < 0) { set_error("strip_rows must be >= 0"); return DEHAZE_EINVAL; }
   if (p->lane_columns < 0 || p->lane_columns > 2) { set_error("lane_columns must be 0, 1 or 2"); return DEHAZE_EINVAL; }
   if (p->stall_window < 0) { set_error("stall_window must be >= 0"); return DEHAZE_EINVAL; }
+  if (p->guided_radius < 0 || p->guided_radius > 1024) {
+    set_error("guided_radius must lie in 0..1024");
+    return DEHAZE_EINVAL;
+  }
+  if (p->guided_radius > 0 && !(p->guided_eps > 0.0 && std::isfinite(p->guided_eps))) {
+    set_error("guided_eps must be positive and finite");
+    return DEHAZE_EINVAL;
+  }
+  if (p->dark_scales < 1 || p->dark_scales > 4) { set_error("dark_scales must lie in 1..4"); return DEHAZE_EINVAL; }
   for (int r : p->reserved)
     if (r != 0) { set_error("reserved fields of dehaze_params must be zero"); return DEHAZE_EINVAL; }
   if (!(p->inner_rtol > 0.0)) { set_error("inner_rtol must be positive"); return DEHAZE_EINVAL; }
@@ -76,9 +85,9 @@ struct PriorPlan {
   size_t bytes = 0;
 };
 
-static PriorPlan plan_prior(void* ws, int H, int W) {
+static PriorPlan plan_prior(void* ws, int H, int W, const dehaze_params& p) {
   PriorPlan pl;
-  pl.bytes = carve_prior(ws, H, W, &pl.b);
+  pl.bytes = carve_prior(ws, H, W, p, &pl.b);
   return pl;
 }
 
@@ -120,6 +129,9 @@ int dehaze_params_default(dehaze_params* p) {
   p->strip_rows = 0;
   p->lane_columns = 0;
   p->stall_window = 256;
+  p->guided_radius = 0;
+  p->dark_scales = 1;
+  p->guided_eps = 1e-3;
   return DEHAZE_OK;
 }
 
@@ -166,9 +178,13 @@ void dehaze_ctx_destroy(dehaze_ctx* ctx) {
 }
 
 size_t dehaze_prior_workspace_size(int H, int W, const dehaze_params* p) {
-  (void)p;
   if (H < 1 || W < 1) return 0;
-  return plan_prior(nullptr, H, W).bytes;
+  dehaze_params d;
+  if (!p) {
+    dehaze_params_default(&d);
+    p = &d;
+  }
+  return plan_prior(nullptr, H, W, *p).bytes;
 }
 
 int dehaze_prior(dehaze_ctx* ctx, const void* I, int dtype, int layout, int H, int W, int pitch,
@@ -181,7 +197,7 @@ int dehaze_prior(dehaze_ctx* ctx, const void* I, int dtype, int layout, int H, i
   if ((rc = check_params(p))) return rc;
   if (!A_out) { set_error("A_out is NULL"); return DEHAZE_EINVAL; }
   if (dark_u8 && dtype != DEHAZE_U8) { set_error("dark_u8 needs 8-bit input"); return DEHAZE_EINVAL; }
-  PriorPlan pl = plan_prior(ws, H, W);
+  PriorPlan pl = plan_prior(ws, H, W, *p);
   if (!ws || ws_bytes < pl.bytes) {
     set_error("prior workspace needs %zu bytes, got %zu", pl.bytes, ws_bytes);
     return DEHAZE_ENOMEM;
@@ -196,7 +212,7 @@ int dehaze_prior(dehaze_ctx* ctx, const void* I, int dtype, int layout, int H, i
     if ((rc = launch_airlight(pl.b, H, W, p->atm_divisor, A_out, s))) return rc;
   }
   FusedOut o{t_d, t, lam, phi, W, W};
-  return launch_prior_fused(pl.b.m, pl.b.Ip, pl.b.P, nullptr, 0, A, H, W, *p, o, s);
+  return launch_prior_estimated(I, dtype, layout, H, W, pitch, *p, pl.b, A, o, s);
 }
 
 size_t dehaze_solve_workspace_size(int H, int W, const dehaze_params* p) {

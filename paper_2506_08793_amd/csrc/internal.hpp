@@ -74,8 +74,13 @@ struct Ctx {
 int launch_to_planar(const void* I, int dtype, int layout, int H, int W, int pitch,
                      float* Ip, int P, hipStream_t s);
 
-// Per-channel patch minimum (van Herk / Gil-Werman, rows then columns) and the
-// raw dark channel.  dark/dark_u8 are dense (pitch W) and nullable.
+// Outputs of the fused t / lambda / Phi pass (all nullable).
+struct FusedOut {
+  float* t_d; float* t; float* lam; float* phi;
+  int op;          // pitch of lam and phi (elements)
+  int tp;          // pitch of t_d and t (elements)
+};
+
 struct PriorBufs {
   float* Ip;      // 3 planes, pitch P: float32 intensities
   float* mrow;    // 3 planes, pitch P: row-pass minima
@@ -83,22 +88,29 @@ struct PriorBufs {
   float* dc;      // 1 plane, pitch P: min over channels
   void* sel;      // airlight selection scratch
   int P;
+  // refinements (carved only when the parameters ask for them)
+  double* tds;    // 1 plane, pitch P: sum of t_d over the dark-channel scales
+  float* traw;    // 1 plane, pitch W: t before the guided filter
+  float* tref;    // 1 plane, pitch W: t after it
+  double* gf;     // 6 planes H x W: guided-filter window sums
 };
 size_t prior_scratch_bytes(int H, int W);
 // Carves the front-end buffers for an H x W image out of `ws` (nullptr: size
 // only); returns the bytes used.
-size_t carve_prior(void* ws, int H, int W, PriorBufs* b);
+size_t carve_prior(void* ws, int H, int W, const dehaze_params& p, PriorBufs* b);
+// t_d, t, lambda and Phi from the patch minima in b (after launch_patch_min
+// and the airlight), with the multiscale dark channel and the guided-filter
+// refinement of t when the parameters ask for them.
+int launch_prior_estimated(const void* I, int dtype, int layout, int H, int W, int pitch, const dehaze_params& p,
+                           const PriorBufs& b, const float* A, const FusedOut& o, hipStream_t s);
+// Per-channel patch minimum (van Herk / Gil-Werman, rows then columns) and the
+// raw dark channel.  dark/dark_u8 are dense (pitch W) and nullable.
 int launch_patch_min(const void* I, int dtype, int layout, int H, int W, int pitch, int patch,
                      const PriorBufs& b, float* dark, uint8_t* dark_u8, hipStream_t s);
 // Dark-channel-prior airlight; writes A_out[3] (device).
 int launch_airlight(const PriorBufs& b, int H, int W, int atm_divisor, float* A_out, hipStream_t s);
 // t_d, t, lambda, Phi from the patch minima (or, with m == nullptr, from a
 // given t) and A.  All outputs nullable; strided outputs use pitch `op`.
-struct FusedOut {
-  float* t_d; float* t; float* lam; float* phi;
-  int op;          // pitch of lam and phi (elements)
-  int tp;          // pitch of t_d and t (elements)
-};
 int launch_prior_fused(const float* m, const float* Ip, int P, const float* t_in, int t_pitch,
                        const float* A, int H, int W, const dehaze_params& p,
                        const FusedOut& o, hipStream_t s);

@@ -476,7 +476,8 @@ struct FusedParams {
 __global__ __launch_bounds__(256) void k_prior_fused(const float* __restrict__ m, const float* __restrict__ Ip,
                                                       int P, const float* __restrict__ t_in, int t_pitch,
                                                       const float* __restrict__ A, int H, int W,
-                                                      FusedParams fp, FusedOut o) {
+                                                      FusedParams fp, FusedOut o, const double* __restrict__ tds,
+                                                      double inv_scales) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y;
   if (x >= W) return;
@@ -485,7 +486,15 @@ __global__ __launch_bounds__(256) void k_prior_fused(const float* __restrict__ m
   const size_t plane = static_cast<size_t>(H) * P;
   const size_t oe = static_cast<size_t>(y) * o.op + x;
   float t32;
-  if (m) {
+  if (tds) {
+    // multiscale: the mean over the scales of the per-scale t_d, rounded once
+    const float td = static_cast<float>(tds[e] * inv_scales);
+    if (o.t_d) o.t_d[static_cast<size_t>(y) * o.tp + x] = td;
+    double t = 1.0 - fp.omega * static_cast<double>(td);
+    t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+    t32 = static_cast<float>(t);
+    if (o.t) o.t[static_cast<size_t>(y) * o.tp + x] = t32;
+  } else if (m) {
     // float64 quotients of float32 operands rounded once to float32 are the
     // correctly rounded float32 quotients; min commutes with that rounding.
     const float q0 = static_cast<float>(static_cast<double>(m[e]) / a0);
@@ -499,6 +508,7 @@ __global__ __launch_bounds__(256) void k_prior_fused(const float* __restrict__ m
     if (o.t) o.t[static_cast<size_t>(y) * o.tp + x] = t32;
   } else {
     t32 = t_in[static_cast<size_t>(y) * t_pitch + x];
+    if (o.t && o.t != t_in) o.t[static_cast<size_t>(y) * o.tp + x] = t32;
   }
   const double t = static_cast<double>(t32);
   if (o.lam) {
@@ -511,6 +521,143 @@ __global__ __launch_bounds__(256) void k_prior_fused(const float* __restrict__ m
     o.phi[oe] = static_cast<float>((static_cast<double>(Ip[e]) - a0 * (1.0 - t)) / den);
     o.phi[oplane + oe] = static_cast<float>((static_cast<double>(Ip[plane + e]) - a1 * (1.0 - t)) / den);
     o.phi[2 * oplane + oe] = static_cast<float>((static_cast<double>(Ip[2 * plane + e]) - a2 * (1.0 - t)) / den);
+  }
+}
+
+// ------------------------------------------------------------ refinements
+// One scale's t_d = min_c fl32(m^c / A^c) (as in the fused pass) added to the
+// float64 sum over the scales of the multiscale dark channel.
+__global__ __launch_bounds__(256) void k_td_acc(const float* __restrict__ m, int P, const float* __restrict__ A,
+                                                 int H, int W, double* __restrict__ tds, int first) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x >= W) return;
+  const size_t e = static_cast<size_t>(y) * P + x;
+  const size_t plane = static_cast<size_t>(H) * P;
+  const float q0 = static_cast<float>(static_cast<double>(m[e]) / static_cast<double>(A[0]));
+  const float q1 = static_cast<float>(static_cast<double>(m[plane + e]) / static_cast<double>(A[1]));
+  const float q2 = static_cast<float>(static_cast<double>(m[2 * plane + e]) / static_cast<double>(A[2]));
+  const double td = static_cast<double>(fminf(fminf(q0, q1), q2));
+  tds[e] = first ? td : tds[e] + td;
+}
+
+// Guided filter (He, Sun and Tang) with the channel mean of I as guide g and
+// t as input q, windows (2r+1)^2 clipped to the image, in float64.  Window
+// sums are sliding sums: one thread walks a row (row passes) or a column
+// (column passes, coalesced across the threads).
+__device__ __forceinline__ double guide_at(const float* Ip, size_t plane, size_t e) {
+  return ((static_cast<double>(Ip[e]) + static_cast<double>(Ip[plane + e])) + static_cast<double>(Ip[2 * plane + e])) /
+         3.0;
+}
+
+// Row window sums of g, q, g^2 and g q into gf[0..3] (dense H x W planes).
+__global__ __launch_bounds__(256) void k_gf_rows4(const float* __restrict__ Ip, int P, const float* __restrict__ q,
+                                                   int qp, int H, int W, int r, double* __restrict__ gf) {
+  const int y = blockIdx.x * blockDim.x + threadIdx.x;
+  if (y >= H) return;
+  const size_t plane = static_cast<size_t>(H) * P, n = static_cast<size_t>(H) * W;
+  auto val = [&](int x, double (&v)[4]) {
+    const double g = guide_at(Ip, plane, static_cast<size_t>(y) * P + x);
+    const double t = q[static_cast<size_t>(y) * qp + x];
+    v[0] = g; v[1] = t; v[2] = g * g; v[3] = g * t;
+  };
+  double sum[4] = {0.0, 0.0, 0.0, 0.0}, v[4];
+  for (int x = 0; x <= r && x < W; ++x) {
+    val(x, v);
+    for (int k = 0; k < 4; ++k) sum[k] += v[k];
+  }
+  for (int x = 0; x < W; ++x) {
+    const size_t o = static_cast<size_t>(y) * W + x;
+    for (int k = 0; k < 4; ++k) gf[k * n + o] = sum[k];
+    if (x + r + 1 < W) {
+      val(x + r + 1, v);
+      for (int k = 0; k < 4; ++k) sum[k] += v[k];
+    }
+    if (x - r >= 0) {
+      val(x - r, v);
+      for (int k = 0; k < 4; ++k) sum[k] -= v[k];
+    }
+  }
+}
+
+__device__ __forceinline__ int win_count(int i, int r, int n) { return min(i + r, n - 1) - max(i - r, 0) + 1; }
+
+// Column window sums of the four row sums -> window means -> a, b of the
+// local linear model, into gf[4], gf[5].
+__global__ __launch_bounds__(256) void k_gf_cols_ab(double* __restrict__ gf, int H, int W, int r, double eps) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= W) return;
+  const size_t n = static_cast<size_t>(H) * W;
+  double sum[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int y = 0; y <= r && y < H; ++y)
+    for (int k = 0; k < 4; ++k) sum[k] += gf[k * n + static_cast<size_t>(y) * W + x];
+  const int cx = win_count(x, r, W);
+  for (int y = 0; y < H; ++y) {
+    const double cnt = static_cast<double>(cx) * win_count(y, r, H);
+    const double mg = sum[0] / cnt, mq = sum[1] / cnt;
+    const double var = sum[2] / cnt - mg * mg, cov = sum[3] / cnt - mg * mq;
+    const double a = cov / (var + eps);
+    const size_t o = static_cast<size_t>(y) * W + x;
+    gf[4 * n + o] = a;
+    gf[5 * n + o] = mq - a * mg;
+    if (y + r + 1 < H)
+      for (int k = 0; k < 4; ++k) sum[k] += gf[k * n + static_cast<size_t>(y + r + 1) * W + x];
+    if (y - r >= 0)
+      for (int k = 0; k < 4; ++k) sum[k] -= gf[k * n + static_cast<size_t>(y - r) * W + x];
+  }
+}
+
+// Row window sums of a and b into gf[0], gf[1].
+__global__ __launch_bounds__(256) void k_gf_rows2(double* __restrict__ gf, int H, int W, int r) {
+  const int y = blockIdx.x * blockDim.x + threadIdx.x;
+  if (y >= H) return;
+  const size_t n = static_cast<size_t>(H) * W, row = static_cast<size_t>(y) * W;
+  double sa = 0.0, sb = 0.0;
+  for (int x = 0; x <= r && x < W; ++x) {
+    sa += gf[4 * n + row + x];
+    sb += gf[5 * n + row + x];
+  }
+  for (int x = 0; x < W; ++x) {
+    gf[row + x] = sa;
+    gf[n + row + x] = sb;
+    if (x + r + 1 < W) {
+      sa += gf[4 * n + row + x + r + 1];
+      sb += gf[5 * n + row + x + r + 1];
+    }
+    if (x - r >= 0) {
+      sa -= gf[4 * n + row + x - r];
+      sb -= gf[5 * n + row + x - r];
+    }
+  }
+}
+
+// Column window sums of those -> mean a, mean b -> out = mean_a g + mean_b,
+// clamped to [0, 1] and rounded once.
+__global__ __launch_bounds__(256) void k_gf_cols_out(const double* __restrict__ gf, const float* __restrict__ Ip,
+                                                      int P, int H, int W, int r, float* __restrict__ out, int op) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= W) return;
+  const size_t n = static_cast<size_t>(H) * W, plane = static_cast<size_t>(H) * P;
+  double sa = 0.0, sb = 0.0;
+  for (int y = 0; y <= r && y < H; ++y) {
+    sa += gf[static_cast<size_t>(y) * W + x];
+    sb += gf[n + static_cast<size_t>(y) * W + x];
+  }
+  const int cx = win_count(x, r, W);
+  for (int y = 0; y < H; ++y) {
+    const double cnt = static_cast<double>(cx) * win_count(y, r, H);
+    const double g = guide_at(Ip, plane, static_cast<size_t>(y) * P + x);
+    double v = (sa / cnt) * g + sb / cnt;
+    v = v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v);
+    out[static_cast<size_t>(y) * op + x] = static_cast<float>(v);
+    if (y + r + 1 < H) {
+      sa += gf[static_cast<size_t>(y + r + 1) * W + x];
+      sb += gf[n + static_cast<size_t>(y + r + 1) * W + x];
+    }
+    if (y - r >= 0) {
+      sa -= gf[static_cast<size_t>(y - r) * W + x];
+      sb -= gf[n + static_cast<size_t>(y - r) * W + x];
+    }
   }
 }
 
@@ -531,9 +678,9 @@ int sel_chunks(int H, int W) {
 
 }  // namespace
 
-size_t carve_prior(void* ws, int H, int W, PriorBufs* b) {
+size_t carve_prior(void* ws, int H, int W, const dehaze_params& p, PriorBufs* b) {
   const int P = padded_pitch(W);
-  const size_t plane = static_cast<size_t>(H) * P;
+  const size_t plane = static_cast<size_t>(H) * P, dense = static_cast<size_t>(H) * W;
   Carver cv(ws, ~size_t(0));
   b->P = P;
   b->Ip = cv.take<float>(3 * plane);
@@ -541,6 +688,10 @@ size_t carve_prior(void* ws, int H, int W, PriorBufs* b) {
   b->m = cv.take<float>(3 * plane);
   b->dc = cv.take<float>(plane);
   b->sel = cv.take<char>(prior_scratch_bytes(H, W));
+  b->tds = p.dark_scales > 1 ? cv.take<double>(plane) : nullptr;
+  b->traw = p.guided_radius > 0 ? cv.take<float>(dense) : nullptr;
+  b->tref = p.guided_radius > 0 ? cv.take<float>(dense) : nullptr;
+  b->gf = p.guided_radius > 0 ? cv.take<double>(6 * dense) : nullptr;
   return cv.used();
 }
 
@@ -613,7 +764,52 @@ int launch_prior_fused(const float* m, const float* Ip, int P, const float* t_in
                        hipStream_t s) {
   FusedParams fp{p.omega, p.t0, p.lambda0, p.beta_lambda, p.adaptive};
   dim3 grid((W + 255) / 256, H);
-  hipLaunchKernelGGL(k_prior_fused, grid, dim3(256), 0, s, m, Ip, P, t_in, t_pitch, A, H, W, fp, o);
+  hipLaunchKernelGGL(k_prior_fused, grid, dim3(256), 0, s, m, Ip, P, t_in, t_pitch, A, H, W, fp, o, nullptr, 0.0);
+  DZ_CHECK_LAUNCH();
+  return DEHAZE_OK;
+}
+
+int launch_prior_estimated(const void* I, int dtype, int layout, int H, int W, int pitch, const dehaze_params& p,
+                           const PriorBufs& b, const float* A, const FusedOut& o, hipStream_t s) {
+  FusedParams fp{p.omega, p.t0, p.lambda0, p.beta_lambda, p.adaptive};
+  const dim3 grid((W + 255) / 256, H);
+  int rc;
+  const int scales = p.dark_scales;
+  if (scales > 1) {
+    // the base scale's minima are in b.m; the other scales overwrite them
+    hipLaunchKernelGGL(k_td_acc, grid, dim3(256), 0, s, b.m, b.P, A, H, W, b.tds, 1);
+    DZ_CHECK_LAUNCH();
+    for (int k = 1; k < scales; ++k) {
+      const int side = ((p.patch - 1) >> k) | 1;
+      if ((rc = launch_patch_min(I, dtype, layout, H, W, pitch, side, b, nullptr, nullptr, s))) return rc;
+      hipLaunchKernelGGL(k_td_acc, grid, dim3(256), 0, s, b.m, b.P, A, H, W, b.tds, 0);
+      DZ_CHECK_LAUNCH();
+    }
+  }
+  const float* m = scales > 1 ? nullptr : b.m;
+  const double* tds = scales > 1 ? b.tds : nullptr;
+  const double inv = 1.0 / scales;
+  if (p.guided_radius <= 0) {
+    hipLaunchKernelGGL(k_prior_fused, grid, dim3(256), 0, s, m, b.Ip, b.P, nullptr, 0, A, H, W, fp, o, tds, inv);
+    DZ_CHECK_LAUNCH();
+    return DEHAZE_OK;
+  }
+  // t before refinement, then the guided filter, then lambda and Phi from it
+  FusedOut o1{o.t_d, b.traw, nullptr, nullptr, o.op, W};
+  hipLaunchKernelGGL(k_prior_fused, grid, dim3(256), 0, s, m, b.Ip, b.P, nullptr, 0, A, H, W, fp, o1, tds, inv);
+  DZ_CHECK_LAUNCH();
+  const int r = p.guided_radius;
+  hipLaunchKernelGGL(k_gf_rows4, dim3((H + 255) / 256), dim3(256), 0, s, b.Ip, b.P, b.traw, W, H, W, r, b.gf);
+  DZ_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_gf_cols_ab, dim3((W + 255) / 256), dim3(256), 0, s, b.gf, H, W, r, p.guided_eps);
+  DZ_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_gf_rows2, dim3((H + 255) / 256), dim3(256), 0, s, b.gf, H, W, r);
+  DZ_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_gf_cols_out, dim3((W + 255) / 256), dim3(256), 0, s, b.gf, b.Ip, b.P, H, W, r, b.tref, W);
+  DZ_CHECK_LAUNCH();
+  FusedOut o2{nullptr, o.t, o.lam, o.phi, o.op, o.tp};
+  hipLaunchKernelGGL(k_prior_fused, grid, dim3(256), 0, s, nullptr, b.Ip, b.P, b.tref, W, A, H, W, fp, o2, nullptr,
+                     0.0);
   DZ_CHECK_LAUNCH();
   return DEHAZE_OK;
 }

@@ -451,13 +451,14 @@ struct BatchPlan {
   size_t bytes = 0;
 };
 
-BatchPlan plan_batch(void* ws, int n, const dehaze_image* im, bool warm) {
+BatchPlan plan_batch(void* ws, int n, const dehaze_image* im, const dehaze_params& p) {
+  const bool warm = p.warm_start != 0;
   BatchPlan pl;
   Carver cv(ws, ~size_t(0));
   size_t prior_max = 0, cnn_max = 0;
   for (int i = 0; i < n; ++i) {
     PriorBufs tmp{};
-    prior_max = std::max(prior_max, carve_prior(nullptr, im[i].H, im[i].W, &tmp));
+    prior_max = std::max(prior_max, carve_prior(nullptr, im[i].H, im[i].W, p, &tmp));
     cnn_max = std::max(cnn_max, cnn_forward_bytes(1, im[i].H, im[i].W));
   }
   pl.prior_ws = cv.take<char>(prior_max);
@@ -491,7 +492,7 @@ BatchPlan plan_batch(void* ws, int n, const dehaze_image* im, bool warm) {
 int batch_front_end(Ctx& ctx, const BatchPlan& pl, int i, const dehaze_image& m, int dtype, int layout,
                     const dehaze_params& p, const float** A_used, hipStream_t s) {
   PriorBufs pb{};
-  carve_prior(pl.prior_ws, m.H, m.W, &pb);
+  carve_prior(pl.prior_ws, m.H, m.W, p, &pb);
   const KImg& K = pl.imgs[i];
   int rc;
   const float* A = m.A;
@@ -511,7 +512,9 @@ int batch_front_end(Ctx& ctx, const BatchPlan& pl, int i, const dehaze_image& m,
   if (m.A && m.A_out && m.A_out != m.A)
     DZ_HIP(hipMemcpyAsync(m.A_out, m.A, 3 * sizeof(float), hipMemcpyDeviceToDevice, s));
   FusedOut fo{nullptr, t_dst, const_cast<float*>(K.lam), const_cast<float*>(K.phi), K.P, m.W};
-  if ((rc = launch_prior_fused(m.t ? nullptr : pb.m, pb.Ip, pb.P, m.t, m.W, A, m.H, m.W, p, fo, s))) return rc;
+  if (m.t) rc = launch_prior_fused(nullptr, pb.Ip, pb.P, m.t, m.W, A, m.H, m.W, p, fo, s);
+  else rc = launch_prior_estimated(m.I, dtype, layout, m.H, m.W, m.pitch, p, pb, A, fo, s);
+  if (rc) return rc;
   if (p.warm_start) {
     const size_t plane = static_cast<size_t>(m.H) * pb.P;
     const float* t_used = m.t ? m.t : t_dst;
@@ -560,7 +563,7 @@ int sweep_shape(const Ctx& ctx, int H, int W, int scheme, int* K, int* S, int* C
 }
 
 size_t batch_workspace_bytes(int n, const dehaze_image* imgs, const dehaze_params& p) {
-  return plan_batch(nullptr, n, imgs, p.warm_start != 0).bytes;
+  return plan_batch(nullptr, n, imgs, p).bytes;
 }
 
 int solve_batch(Ctx& ctx, int n, const dehaze_image* im, int dtype, int layout, const dehaze_params& p, void* ws,
@@ -569,7 +572,7 @@ int solve_batch(Ctx& ctx, int n, const dehaze_image* im, int dtype, int layout, 
   for (int i = 0; i < n; ++i) any_u0 = any_u0 || im[i].u0;
   int rc0 = check_warm(ctx, p, any_u0);
   if (rc0) return rc0;
-  BatchPlan pl = plan_batch(ws, n, im, p.warm_start != 0);
+  BatchPlan pl = plan_batch(ws, n, im, p);
   std::vector<const float*> A_used(n, nullptr), u0(n, nullptr);
   int rc;
   for (int i = 0; i < n; ++i) {

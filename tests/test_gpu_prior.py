@@ -114,3 +114,61 @@ def test_prior_rejects_bad_arguments():
         with pytest.raises(d.DehazeError) as e:
             d.dehaze_prior(ctx(), img, params=d.dehaze_params_default(**kw))
         assert e.value.code == -1
+
+
+# Refinements (readings of the guided filter and multiscale dark channel that
+# Table II ablates).  t_d of several scales is a mean of per-scale float32
+# t_d summed in float64: within one float32 ulp of the oracle's float64 mean.
+# The guided filter is linear in its input with gain at most about
+# max|g - mean g| / (var g + eps) per window (~30 at eps = 1e-3), so a one-ulp
+# difference in its input moves the output by at most ~30 ulps; with equal
+# inputs only the summation order differs (one rounding at the end).
+@pytest.mark.parametrize("H,W,seed", [(37, 53, 16), (64, 64, 1000), (130, 70, 17), (5, 300, 13), (1, 1, 11)])
+@pytest.mark.parametrize("radius,scales", [(0, 2), (0, 3), (4, 1), (8, 3), (20, 2)])
+def test_prior_refinements_parity(H, W, seed, radius, scales):
+    require_gpu()
+    import paper_2506_08793_amd as d
+    img = synth.hazy_image(H, W, seed, beta_haze=(0.5, 2.0), occlusion=True)
+    q = o.with_params(guided_radius=radius, dark_scales=scales, guided_eps=1e-3)
+    ref = o.prior(img["I"], q)
+    say(f"prior refinements H={H} W={W} r={radius} scales={scales}")
+    p = d.dehaze_params_default(guided_radius=radius, dark_scales=scales, guided_eps=1e-3)
+    out = d.dehaze_prior(ctx(), dev(img["I"]), params=p, outputs=("dark", "t_d", "t", "lam", "phi"))
+    got = {k: host(v) for k, v in out.items() if not k.startswith("_")}
+    assert np.array_equal(got["dark"], ref["dc"].astype(np.float32))
+    assert np.array_equal(got["A"].astype(np.float64), ref["A"])
+    td32 = ref["t_d"].astype(np.float32)
+    if scales == 1:
+        assert np.array_equal(got["t_d"], td32)
+    else:
+        assert np.all(np.abs(got["t_d"] - td32) <= np.spacing(td32))
+    if radius == 0:
+        t_tol = T_TOL if scales == 1 else 2.0 * T_TOL
+    else:
+        t_tol = 2.0 ** -23 if scales == 1 else 30 * 2.0 ** -24
+    err = np.max(np.abs(got["t"] - ref["t"]))
+    say(f"  max |dt| {err:.3e} (bound {t_tol:.3e})")
+    assert err <= t_tol
+    # lambda and Phi of the library's own t
+    t_own = got["t"].astype(np.float64)
+    lam_own = o.adaptive_weight(t_own)
+    phi_own = o.reconstruction(img["I"], t_own, got["A"].astype(np.float64), 0.1)
+    assert np.max(np.abs(got["lam"] - lam_own) / lam_own) <= 2.0 ** -23
+    assert np.all(np.abs(got["phi"] - phi_own) <= 2.0 ** -23 * np.abs(phi_own) + 1e-12)
+
+
+def test_batch_front_end_applies_refinements():
+    # the batch's own front end (t estimated inside) equals dehaze_prior +
+    # dehaze_solve with the same parameters, bit for bit
+    require_gpu()
+    import paper_2506_08793_amd as d
+    imgs = [synth.hazy_image(h, w, 40 + k, beta_haze=(0.5, 2.0), occlusion=True)["I"]
+            for k, (h, w) in enumerate([(48, 40), (33, 70)])]
+    p = d.dehaze_params_default(guided_radius=6, dark_scales=2, max_outer=20, rel_tol=0.0)
+    say("batch front end with refinements")
+    ub, _, tb, Ab = d.dehaze_batch(ctx(), [dev(I) for I in imgs], params=p, want_t=True)
+    for k, I in enumerate(imgs):
+        pr = d.dehaze_prior(ctx(), dev(I), params=p, outputs=("t",))
+        assert np.array_equal(host(tb[k]), host(pr["t"]))
+        us, _ = d.dehaze_solve(ctx(), dev(I), pr["t"], pr["A"], params=p)
+        assert np.array_equal(host(ub[k]), host(us))
