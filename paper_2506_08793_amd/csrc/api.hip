@@ -115,10 +115,10 @@ int dehaze_params_default(dehaze_params* p) {
   p->tau = 0.2;
   p->theta = 0.8;
   p->rel_tol = 1e-5;
-  p->inner_rtol = 0.1;
+  p->inner_rtol = 0.2;
   p->scheme = DEHAZE_PICARD_KRYLOV;
   p->max_outer = 5000;
-  p->max_inner = 30;
+  p->max_inner = 64;
   p->check_every = 16;
   p->atm_divisor = 1000;
   p->warm_start = 0;
