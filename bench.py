@@ -111,6 +111,7 @@ def images_per_second(d, ctx, n: int, warm: bool, seed0: int = 7000) -> dict:
             "applications_mean": float(np.mean([x["applications"] for x in st])),
             "converged": int(sum(x["converged"] for x in st)),
             "rel_residual_max": float(max(x["rel_residual"] for x in st)),
+            "rel_residual_out_max": float(max(x["rel_residual_out"] for x in st)),
             "rel_residual0_mean": float(np.mean([x["rel_residual0"] for x in st])), "_u": u}
 
 
@@ -165,7 +166,8 @@ def batch_workload(d, ctx, name: str) -> dict:
             "mpx_per_s": round(mpx / dt, 3),
             "outer_mean": float(np.mean([x["outer"] for x in st])), "outer_max": int(max(x["outer"] for x in st)),
             "converged": int(sum(x["converged"] for x in st)), "restarts": int(sum(x["restarts"] for x in st)),
-            "rel_residual_max": float(max(x["rel_residual"] for x in st))}
+            "rel_residual_max": float(max(x["rel_residual"] for x in st)),
+            "rel_residual_out_max": float(max(x["rel_residual_out"] for x in st))}
         print(f"[bench] {name} {'warm' if warm else 'cold'}: {out['warm' if warm else 'cold']}", file=sys.stderr,
               flush=True)
         del u

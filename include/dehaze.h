@@ -116,12 +116,19 @@ typedef struct dehaze_stats {
   int32_t converged;        /* 1 if rel_tol was reached */
   int64_t inner;            /* BiCGSTAB iterations in total */
   int64_t applications;     /* operator applications (sweeps or matrix-vector products) */
-  double  rel_residual;     /* ||Phi - L_{D(u)} u|| / ||Phi|| at the returned u (float64 sum) */
+  double  rel_residual;     /* ||Phi - L_{D(u)} u|| / ||Phi|| (float64 sum) at the final iterate; the
+                               lagged-diffusivity solves iterate in float64, and rel_tol is tested
+                               against this value */
   double  rel_residual0;    /* the same at the starting iterate */
   float   A[3];             /* atmospheric light used */
   int32_t status;           /* DEHAZE_OK, DEHAZE_ENOTCONV or DEHAZE_ENONFINITE for this image */
   int32_t restarts;         /* 1 if the solve stalled from its given start and restarted from Phi */
   int32_t stalled;          /* 1 if the solve stopped early because rho stopped falling */
+  double  rel_residual_out; /* the same residual at the returned float32 u.  Rounding u to float32
+                               perturbs each flux by up to ulp(u) / eps, so where u is large and flat
+                               this sits at a floor well above rel_residual (e.g. 7.6e-4 for a 1080p
+                               image with u near 32 whose iterate met 1e-5); the sweep schemes iterate
+                               in float32 and report rel_residual here too */
 } dehaze_stats;
 
 typedef struct dehaze_ctx dehaze_ctx;

@@ -51,14 +51,14 @@ class Stats(ctypes.Structure):
     _fields_ = [
         ("outer", c_int32), ("converged", c_int32), ("inner", c_int64), ("applications", c_int64),
         ("rel_residual", c_double), ("rel_residual0", c_double), ("A", c_float * 3), ("status", c_int32),
-        ("restarts", c_int32), ("stalled", c_int32),
+        ("restarts", c_int32), ("stalled", c_int32), ("rel_residual_out", c_double),
     ]
 
     def as_dict(self) -> dict:
         return {"outer": self.outer, "converged": bool(self.converged), "inner": self.inner,
                 "applications": self.applications, "rel_residual": self.rel_residual,
                 "rel_residual0": self.rel_residual0, "A": list(self.A), "status": self.status,
-                "restarts": self.restarts, "stalled": self.stalled}
+                "restarts": self.restarts, "stalled": self.stalled, "rel_residual_out": self.rel_residual_out}
 
 
 class Image(ctypes.Structure):

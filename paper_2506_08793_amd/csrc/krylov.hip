@@ -236,7 +236,10 @@ __global__ __launch_bounds__(NT) void k_res(const KImg* __restrict__ imgs, KScal
       const int yy = tp.y0 - HALO + ly, xx = tp.x0 - HALO + lx;
       const bool in = yy >= 0 && yy < I.H && xx >= 0 && xx < I.W;
       const size_t e = static_cast<size_t>(yy) * I.P + xx;
-      us[ly][lx] = in ? (restart ? static_cast<double>(pc[e]) : uc[e]) : 0.0;
+      // the output pass reads the iterate as the float32 value it is returned as
+      us[ly][lx] = in ? (restart ? static_cast<double>(pc[e])
+                                 : (final == 2 ? static_cast<double>(static_cast<float>(uc[e])) : uc[e]))
+                      : 0.0;
       if (LINEAR) ud[ly][lx] = in ? unc[e] : 0.0;
     }
     if (restart) {
@@ -320,6 +323,10 @@ __global__ __launch_bounds__(NT) void k_red_res(const KImg* __restrict__ imgs, K
   double tot[3];
   image_sums<3>(I, part, tot);
   if (threadIdx.x != 0) return;
+  if (!LINEAR && final == 2) {
+    sc->rel_out = tot[1] > 0.0 ? sqrt(tot[0] / tot[1]) : sqrt(tot[0]);
+    return;
+  }
   if (!LINEAR) {
     if (sc->inner_this > 0) {  // account for the update applied since the last pass
       sc->outer += 1;

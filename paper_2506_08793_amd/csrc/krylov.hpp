@@ -76,6 +76,7 @@ struct KScal {
   int restart;             // restart from Phi at the next residual pass
   int restarted;           // restarted once already
   int stalled;             // stopped: rho stopped falling (tolerance-terminated solves)
+  double rel_out;          // rho of the iterate rounded to float32 (the returned u)
 };
 
 struct KConst {

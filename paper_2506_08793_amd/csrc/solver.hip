@@ -215,6 +215,7 @@ int run_sweeps(Ctx& ctx, const SolveArgs& a, const dehaze_params& p, dehaze_stat
     st->applications = done;
     st->rel_residual = rho;
     st->rel_residual0 = rho0;
+    st->rel_residual_out = rho;
     st->restarts = 0;
     st->stalled = 0;
     DZ_HIP(hipMemcpyAsync(st->A, a.A, 3 * sizeof(float), hipMemcpyDeviceToHost, s));
@@ -275,6 +276,7 @@ void fill_stats(const KScal& k, dehaze_stats* st) {
   st->applications = 2 * k.inner_total + k.res_evals;
   st->rel_residual = k.rel;
   st->rel_residual0 = k.rel0;
+  st->rel_residual_out = k.rel_out;
   st->status = k.nonfinite ? DEHAZE_ENONFINITE : DEHAZE_OK;
   st->restarts = k.restarted;
   st->stalled = k.stalled;
@@ -385,6 +387,9 @@ int krylov_loop(Ctx& ctx, const KrylovBatch& b, const dehaze_params& p, KScal* h
     }
   }
   if ((rc = krylov_residual(b, kc, 1, s))) return rc;
+  // the float64 iterate is returned rounded to float32; its residual there
+  // is reported beside the iterate's own
+  if ((rc = krylov_residual(b, kc, 2, s))) return rc;
   if (need_scalars || p.rel_tol > 0.0) return read_scalars(b, h, s);
   return DEHAZE_OK;
 }

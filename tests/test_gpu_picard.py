@@ -4,12 +4,15 @@ import numpy as np
 import pytest
 
 import synth
-from gpu_util import ctx, dev, host, require_gpu, say
+from gpu_util import ctx, dev, host, require_gpu, say, ulp32
 from oracle import dehaze_ref as o
 
 pytestmark = pytest.mark.gpu
 
 U_TOL = 1e-4
+# absolute slack on a relative residual formed from float32 Phi and lambda
+# (a few 1e-7 per pixel, summed in float64)
+RHO_ABS = 4e-6
 
 
 def _inputs(H, W, seed, beta=1.0, occlusion=False):
@@ -98,6 +101,8 @@ def test_picard_reaches_tolerance():
     say(f"  oracle rho of float32 output {rho_gpu_u:.3e}, float32 floor {floor:.3e}, "
         f"max-abs vs converged {np.max(np.abs(u - ref.u)):.3e}")
     assert rho_gpu_u <= 2.0 * floor + 2e-5
+    # the residual the library reports for its float32 output is that of u
+    assert abs(rho_gpu_u - st["rel_residual_out"]) <= 1e-4 * rho_gpu_u + RHO_ABS
     assert np.max(np.abs(u - ref.u)) <= 1e-2
 
 
@@ -157,3 +162,33 @@ def test_network_start_that_stalls_is_restarted():
     assert stc["converged"] and stw["converged"] and stc["stalled"] == 0 and stw["stalled"] == 0
     assert stw["restarts"] == 1
     assert np.array_equal(host(uw), host(uc))
+
+
+def test_picard_full_size_1080p():
+    # The 1080p workload of the images/s figure (held-out seed 7000), default
+    # settings.  The float64 iterate meets rel_tol = 1e-5; the returned float32
+    # u carries the rounding floor of float32 (u near 32, flux slope up to
+    # 1/eps): the library reports that residual too, the oracle's float64
+    # residual of the returned u must agree with it, and a further random
+    # half-ulp perturbation of u must not lower it (u is as close to the
+    # iterate as float32 allows, not merely near it).
+    require_gpu()
+    import paper_2506_08793_amd as d
+    img = synth.hazy_image(1080, 1920, 7000, beta_haze=(0.5, 2.5), occlusion=True)
+    say("picard 1080p to 1e-5 (defaults)")
+    I = dev(img["I"])
+    pg = d.dehaze_prior(ctx(), I, outputs=("t",))
+    u, st = d.dehaze_solve(ctx(), I, pg["t"], pg["A"], params=d.dehaze_params_default())
+    say(f"  {st}")
+    assert st["converged"] and st["rel_residual"] <= 1e-5 and st["stalled"] == 0
+    pr = o.prior(img["I"])
+    uh = host(u).astype(np.float64)
+    assert np.all(np.isfinite(uh))
+    _, rho = o.residual(uh, pr["phi"], pr["lam"])
+    rng = np.random.default_rng(7)
+    nudge = np.where(rng.random(uh.shape) < 0.5, -0.5, 0.5) * ulp32(uh)
+    _, rho_nudged = o.residual(uh + nudge, pr["phi"], pr["lam"])
+    say(f"  oracle rho of the float32 output {rho:.3e}, library {st['rel_residual_out']:.3e}, "
+        f"after a half-ulp nudge {rho_nudged:.3e}")
+    assert abs(rho - st["rel_residual_out"]) <= 1e-4 * rho + RHO_ABS
+    assert st["rel_residual"] <= rho <= rho_nudged

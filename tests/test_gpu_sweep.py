@@ -88,6 +88,7 @@ def test_jacobi_stops_on_tolerance():
     say("jacobi rel_tol")
     u, st = _gpu_solve(I, t32, A32, scheme=1, max_outer=400, rel_tol=0.9, check_every=4)
     assert st["converged"] and st["rel_residual"] <= 0.9 and st["outer"] % 4 == 0
+    assert st["rel_residual_out"] == st["rel_residual"]  # float32 iterate: the output itself
     _, rho = o.residual(u.astype(np.float64), phi, lam)
     assert rho_close(st["rel_residual"], rho, 1e-5)
     # not reachable: ENOTCONV is returned as a status, u holds the last iterate
