@@ -253,15 +253,23 @@ struct StripLevel {
   float ph[C][PF], la[C][PF];
 };
 
+// fs, feps, fone: the face coefficient is formed as 1 / (fs |g| + feps), or
+// fone without edge preservation.  The explicit update takes fs = fone = 1,
+// feps = eps, i.e. D itself.  The Jacobi update takes D / theta (fs = theta,
+// feps = theta eps, fone = 1 / theta) and wc2 / theta, which folds the
+// damping into the diagonal: theta r / d = (Phi - lambda G + theta div') / d'
+// with div' and d' formed from D / theta.
 struct StripConst {
-  float w0, w1, w2, eps, wc2, theta, tau;
+  float w0, w1, w2, wc2, theta, tau;
+  float fs, feps, fone;
 };
 
-// Face coefficient 1 / (|(gn, gt)| + eps) of Appendix A-2, or 1 without edge
-// preservation.
+// Face coefficient 1 / (|(gn, gt)| + eps) of Appendix A-2 (scaled as above),
+// or its value without edge preservation.
 template <bool EDGE>
-__device__ __forceinline__ float strip_face(float gn, float gt, float eps) {
-  return EDGE ? __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(__builtin_fmaf(gn, gn, gt * gt)) + eps) : 1.0f;
+__device__ __forceinline__ float strip_face(float gn, float gt, const StripConst& k) {
+  return EDGE ? __builtin_amdgcn_rcpf(__builtin_fmaf(k.fs, __builtin_amdgcn_sqrtf(__builtin_fmaf(gn, gn, gt * gt)), k.feps))
+              : k.fone;
 }
 
 // Values at column offset d (-2..2) of every column of the lane: columns
@@ -314,18 +322,18 @@ __device__ __forceinline__ void strip_level(StripLevel<C, PF>& L, const float (&
       if (FIRST) {
         const float gny_t = u0 - up;
         const float gty_t = 0.5f * (L.SR[c][1] - L.SL[c][1]);
-        L.DT[c] = strip_face<EDGE>(gny_t, gty_t, k.eps);
+        L.DT[c] = strip_face<EDGE>(gny_t, gty_t, k);
         L.qT[c] = L.DT[c] * gny_t;
       }
       // face right of (x, j): normal u(x+1) - u(x), tangential at this cell
       const float gnx = L.SR[c][2] - u0;
       const float gtx = 0.5f * (dn - up);
-      DR[c] = strip_face<EDGE>(gnx, gtx, k.eps);
+      DR[c] = strip_face<EDGE>(gnx, gtx, k);
       qR[c] = DR[c] * gnx;
       // face below (x, j): normal u(j+1) - u(j), tangential at this cell
       const float gny = dn - u0;
       const float gty = 0.5f * (L.SR[c][2] - L.SL[c][2]);
-      DB[c] = strip_face<EDGE>(gny, gty, k.eps);
+      DB[c] = strip_face<EDGE>(gny, gty, k);
       qB[c] = DB[c] * gny;
     }
     // the face left of column 0 is the right face of the left lane's last column
@@ -338,12 +346,14 @@ __device__ __forceinline__ void strip_level(StripLevel<C, PF>& L, const float (&
           __builtin_fmaf(k.w2, L.GH[c][0] + ghn[c], __builtin_fmaf(k.w1, L.GH[c][1] + L.GH[c][3], k.w0 * L.GH[c][2]));
       const float div = (qR[c] - qL) + (qB[c] - L.qT[c]);
       const float phc = L.ph[c][q], lac = L.la[c][q];
-      const float r_ = phc - __builtin_fmaf(lac, G, -div);
       if (MODE == kExplicit) {
+        const float r_ = phc - __builtin_fmaf(lac, G, -div);
         out[c] = __builtin_fmaf(k.tau, r_, u0);
       } else {
+        // theta r, with div and d formed from D / theta
+        const float r_ = __builtin_fmaf(k.theta, div, __builtin_fmaf(-lac, G, phc));
         const float d = __builtin_fmaf(lac, k.wc2, (DL + DR[c]) + (L.DT[c] + DB[c]));
-        out[c] = __builtin_fmaf(k.theta * r_, __builtin_amdgcn_rcpf(d), u0);
+        out[c] = __builtin_fmaf(r_, __builtin_amdgcn_rcpf(d), u0);
       }
       L.qT[c] = qB[c];
       L.DT[c] = DB[c];
@@ -420,9 +430,18 @@ __global__ __launch_bounds__(64 * kStripWaves) void k_sweep_strip(const float* _
   k.w0 = nl ? oc.w[2] : 0.0f;
   k.w1 = nl ? oc.w[1] : 0.0f;
   k.w2 = nl ? oc.w[0] : 0.0f;
-  k.wc2 = nl ? oc.wc2 : 0.0f;
-  k.eps = oc.eps;
   k.theta = oc.theta;
+  if (MODE == kJacobi) {
+    k.fs = oc.theta;
+    k.feps = oc.theta * oc.eps;
+    k.fone = 1.0f / oc.theta;
+    k.wc2 = nl ? oc.wc2 / oc.theta : 0.0f;
+  } else {
+    k.fs = 1.0f;
+    k.feps = oc.eps;
+    k.fone = 1.0f;
+    k.wc2 = nl ? oc.wc2 : 0.0f;
+  }
   k.tau = oc.tau;
 
   // Loads are unconditional from clamped rows and columns.  u of a row or
