@@ -91,15 +91,15 @@ def cpu_baseline(img, sweeps: int = 6) -> dict:
             "front_end_s": round(t1 - t0, 3), "sweep_s": round(sweep_s, 3)}
 
 
-def images_per_second(d, ctx, n: int, warm: bool, seed0: int = 7000) -> dict:
+def images_per_second(d, ctx, n: int, warm: int, seed0: int = 7000) -> dict:
     """Solve n held-out 1920x1080 images to rho <= 1e-5 in one batch call
-    (front end, network when warm, lagged-diffusivity solve); inputs are on
-    the device before the clock starts."""
+    (front end, the warm start warm_start = warm selects, lagged-diffusivity
+    solve); inputs are on the device before the clock starts."""
     import torch
     import synth
     imgs = [torch.from_numpy(synth.hazy_image(1080, 1920, seed0 + k, beta_haze=(0.5, 2.5), occlusion=True)["I"]).cuda()
             for k in range(n)]
-    p = d.dehaze_params_default(max_outer=6000, rel_tol=1e-5, warm_start=1 if warm else 0)
+    p = d.dehaze_params_default(max_outer=6000, rel_tol=1e-5, warm_start=warm)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     u, st, _, _ = d.dehaze_batch(ctx, imgs, params=p)
@@ -118,19 +118,24 @@ def images_per_second(d, ctx, n: int, warm: bool, seed0: int = 7000) -> dict:
 def secondary(d, ctx, n: int) -> dict:
     from paper_2506_08793_amd import warmstart
     meta = warmstart.load(ctx, warmstart.default_weights_path())
-    cold = images_per_second(d, ctx, n, warm=False)
-    warm = images_per_second(d, ctx, n, warm=True)
-    diff = max(float((a - b).abs().max()) for a, b in zip(cold.pop("_u"), warm.pop("_u")))
+    cold = images_per_second(d, ctx, n, warm=0)
+    analytic = images_per_second(d, ctx, n, warm=2)
+    warm = images_per_second(d, ctx, n, warm=1)
+    uc = cold.pop("_u")
+    diff = max(float((a - b).abs().max()) for a, b in zip(uc, warm.pop("_u")))
+    analytic.pop("_u")
     return {"workload": f"{n} held-out synthetic 1920x1080 RGB float32 hazy images (seeds 7000+, beta_haze~U(0.5,2.5), "
                         f"occlusion edges), one dehaze_batch call each, to relative residual 1e-5",
-            "cold": cold, "warm": warm, "warm_speedup": round(cold["seconds"] / warm["seconds"], 3),
+            "cold": cold, "analytic": analytic, "warm": warm,
+            "warm_speedup": round(cold["seconds"] / warm["seconds"], 3),
+            "analytic_speedup": round(cold["seconds"] / analytic["seconds"], 3),
             "outer_steps_saved": round(1.0 - warm["outer_mean"] / cold["outer_mean"], 3),
             "max_abs_warm_vs_cold": diff,
             "network": {"trained_on": f"{meta.get('images')} images {meta.get('size')}", "steps": meta.get("steps")}}
 
 
 def batch_workload(d, ctx, name: str) -> dict:
-    """Images/s of one dehaze_batch call to rho <= 1e-5, cold and network-warm.
+    """Images/s of one dehaze_batch call to rho <= 1e-5: cold, analytic start, network-warm.
 
     batch64: 64 images of sizes drawn uniformly from {256x256, 640x480, 1280x720,
     1920x1080, 2048x1536} (seeds 3000+); serving: 16 images of 3840x2160 plus 48
@@ -154,21 +159,22 @@ def batch_workload(d, ctx, name: str) -> dict:
     mpx = sum(h * w for h, w in sizes) / 1e6
     warmstart.load(ctx, warmstart.default_weights_path())
     out = {"workload": name, "images": len(sizes), "mpx": round(mpx, 2)}
-    for warm in (0, 1):
+    for warm in (0, 2, 1):
         p = d.dehaze_params_default(max_outer=6000, rel_tol=1e-5, warm_start=warm)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         u, st, _, _ = d.dehaze_batch(ctx, imgs, params=p)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        out["warm" if warm else "cold"] = {
+        out[("cold", "warm", "analytic")[warm]] = {
             "images_per_s": round(len(sizes) / dt, 4), "seconds": round(dt, 3),
             "mpx_per_s": round(mpx / dt, 3),
             "outer_mean": float(np.mean([x["outer"] for x in st])), "outer_max": int(max(x["outer"] for x in st)),
             "converged": int(sum(x["converged"] for x in st)), "restarts": int(sum(x["restarts"] for x in st)),
             "rel_residual_max": float(max(x["rel_residual"] for x in st)),
             "rel_residual_out_max": float(max(x["rel_residual_out"] for x in st))}
-        print(f"[bench] {name} {'warm' if warm else 'cold'}: {out['warm' if warm else 'cold']}", file=sys.stderr,
+        key = ("cold", "warm", "analytic")[warm]
+        print(f"[bench] {name} {key}: {out[key]}", file=sys.stderr,
               flush=True)
         del u
     return out

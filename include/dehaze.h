@@ -84,8 +84,11 @@ typedef struct dehaze_params {
   int32_t max_inner;        /* BiCGSTAB iterations per lagged-diffusivity step */
   int32_t check_every;      /* residual test every this many outer steps (>= 1) */
   int32_t atm_divisor;      /* A from the top max(1, HW / atm_divisor) dark-channel pixels */
-  int32_t warm_start;       /* 1: start the lagged-diffusivity solve from the network's prediction
-                               (needs loaded weights; u0 must then be NULL) */
+  int32_t warm_start;       /* starting iterate of the lagged-diffusivity solve (u0 must then be NULL):
+                               0 = Phi (or u0); 2 = B = Phi / lambda, the solution of lambda u = Phi,
+                               to which the main PDE reduces where u is smooth (B = Phi without the
+                               nonlocal term or with lambda = 0); 1 = B plus the network's learned
+                               correction (needs loaded weights) */
   int32_t nonlocal_term;    /* 0: drop lambda G (ablation) */
   int32_t adaptive;         /* 0: lambda = lambda0 everywhere (ablation) */
   int32_t edge_preserving;  /* 0: D = 1 (ablation; the solve becomes linear) */
@@ -99,7 +102,7 @@ typedef struct dehaze_params {
   int32_t lane_columns;     /* adjacent columns per lane of that kernel (1 or 2); 0 = tuned */
   int32_t stall_window;     /* lagged-diffusivity solves: if over this many outer steps the lowest rho did
                                not fall below half its value at the window's start, an image that
-                               started from a given iterate (u0 or the network) restarts once from Phi;
+                               started from a given iterate (u0 or a warm start) restarts once from Phi;
                                otherwise, when rel_tol > 0, its solve stops there (DEHAZE_ENOTCONV,
                                stats.stalled = 1).  0 = never; default 256 */
   int32_t guided_radius;    /* > 0: refine the estimated t with a guided filter (guide: channel mean of I,
@@ -181,7 +184,7 @@ int dehaze_prior(dehaze_ctx* ctx, const void* I, int dtype, int layout, int H, i
 /* ------------------------------------------------------------ one image solve
  * Builds lambda(t) and Phi(I, t, A) from the given t (H x W, pitch W) and A
  * (3 device floats), then iterates p->scheme from u0 (planar, pitch W;
- * NULL = Phi, or the network when p->warm_start) into u (planar, pitch W).
+ * NULL = Phi, or the warm start p->warm_start selects) into u (planar, pitch W).
  *   DEHAZE_PAPER_EXPLICIT, DEHAZE_JACOBI: p->max_outer sweeps, each one pass
  *     of the face-coefficient recompute and the update (Appendix A-1).
  *   DEHAZE_PICARD_KRYLOV: lagged-diffusivity steps; the residual of the
@@ -229,13 +232,15 @@ int dehaze_batch(dehaze_ctx* ctx, int n, const dehaze_image* imgs, int dtype, in
 
 /* ------------------------------------------------------------ warm-start network
  * The paper ends its introduction by pointing at hybrids of the PDE with
- * learned models; this network supplies the starting iterate of the
- * lagged-diffusivity solve (warm_start = 1), which then runs to its own
- * residual test exactly as from a cold start.  Architecture: six 3x3
- * convolutions 7 -> 32 -> 32 -> 32 -> 32 -> 32 -> 3, ReLU after the first
- * five, zero padding, input [I^R, I^G, I^B, t, A^R, A^G, A^B] per pixel,
- * output u / 8 (the prediction is multiplied by 8).  bfloat16 weights and
- * activations, float32 accumulation on the matrix cores.
+ * learned models; this network corrects the analytic start B = Phi / lambda
+ * (see warm_start): the lagged-diffusivity solve starts from B + network
+ * (warm_start = 1) and then runs to its own residual test exactly as from a
+ * cold start.  The network is trained on u* - B for converged solutions u*.
+ * Architecture: six 3x3 convolutions 7 -> 32 -> 32 -> 32 -> 32 -> 32 -> 3,
+ * ReLU after the first five, zero padding, input [I^R, I^G, I^B, t, A^R,
+ * A^G, A^B] per pixel, output (u - B) / 8 (dehaze_cnn_forward returns the
+ * output multiplied by 8, i.e. the correction itself).  bfloat16 weights
+ * and activations, float32 accumulation on the matrix cores.
  *
  * Parameters are float32 on the host, layer by layer: W[co][ci][3][3] then
  * b[co] (dehaze_cnn_param_count() values in all).  The context keeps a
@@ -248,7 +253,7 @@ size_t dehaze_cnn_param_count(void);
 int dehaze_cnn_set_weights(dehaze_ctx* ctx, const float* w, size_t count);   /* host; resets Adam */
 int dehaze_cnn_get_weights(dehaze_ctx* ctx, float* w, size_t count);         /* host */
 size_t dehaze_cnn_workspace_size(int n, int H, int W, int training);
-/* u (n x 3 x H x W planar) = the network's prediction. */
+/* u (n x 3 x H x W planar) = the network's output times 8: its correction to B. */
 int dehaze_cnn_forward(dehaze_ctx* ctx, int n, int H, int W, const float* I, const float* t, const float* A,
                        float* u, void* ws, size_t ws_bytes, void* stream);
 /* Gradient of the loss wrt the parameters (device, param_count floats, layout

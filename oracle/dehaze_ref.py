@@ -37,6 +37,8 @@ Readings taken where the paper is silent or ambiguous (all are parameters):
     filter with the channel-mean guide; t_d averaged over patch sides patch,
     patch/2, ...) are off by default and parity unpinned against the paper:
     their tests pin them to brute force and closed forms only.
+  * The warm start begins from B = Phi / lambda, the solution of lambda u =
+    Phi to which the main PDE reduces where u is smooth (analytic_start).
   * Three iterations share the fixed point r(u) = 0: the paper's explicit
     relaxed update, a diagonally scaled (Jacobi) form of it, and the
     lagged-diffusivity (Picard) iteration u_{n+1} = L(D(u_n))^-1 Phi.
@@ -222,6 +224,20 @@ def reconstruction(I: np.ndarray, t: np.ndarray, A, t0: float) -> np.ndarray:
     t = np.asarray(t, dtype=np.float64)
     A = np.asarray(A, dtype=np.float64)
     return (I - A[:, None, None] * (1.0 - t[None])) / np.maximum(t, t0)[None]
+
+
+def analytic_start(phi: np.ndarray, lam: np.ndarray, p: Params = DEFAULT) -> np.ndarray:
+    """B = Phi / lambda: where u is smooth, G(u) = u and the diffusion term of
+    the main PDE vanishes, leaving lambda u = Phi.  Without the nonlocal term
+    (or where lambda = 0) B = Phi.  A starting iterate, not part of the
+    method; the warm start of the solve (a reading, Section I's closing
+    remark on hybrids)."""
+    phi = np.asarray(phi, dtype=np.float64)
+    lam = np.broadcast_to(np.asarray(lam, dtype=np.float64), phi.shape[-2:])
+    if not p.nonlocal_term:
+        return phi.copy()
+    safe = np.where(lam > 0, lam, 1.0)
+    return np.where(lam[None] > 0, phi / safe[None], phi)
 
 
 def prior(I: np.ndarray, p: Params = DEFAULT, A=None) -> dict:

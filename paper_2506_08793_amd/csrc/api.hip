@@ -54,6 +54,7 @@ int check_params(const dehaze_params* p) {
   if (p->strip_rows < 0) { set_error("strip_rows must be >= 0"); return DEHAZE_EINVAL; }
   if (p->lane_columns < 0 || p->lane_columns > 2) { set_error("lane_columns must be 0, 1 or 2"); return DEHAZE_EINVAL; }
   if (p->stall_window < 0) { set_error("stall_window must be >= 0"); return DEHAZE_EINVAL; }
+  if (p->warm_start < 0 || p->warm_start > 2) { set_error("warm_start must be 0, 1 or 2"); return DEHAZE_EINVAL; }
   if (p->guided_radius < 0 || p->guided_radius > 1024) {
     set_error("guided_radius must lie in 0..1024");
     return DEHAZE_EINVAL;

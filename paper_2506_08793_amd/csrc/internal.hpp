@@ -115,6 +115,11 @@ int launch_prior_fused(const float* m, const float* Ip, int P, const float* t_in
                        const float* A, int H, int W, const dehaze_params& p,
                        const FusedOut& o, hipStream_t s);
 
+// Warm start u0 (planar, pitch W) = B (+ u0 when add), B = Phi / lambda, or Phi
+// without the nonlocal term; Phi and lambda have pitch P.
+int launch_warm_base(float* u0, const float* phi, const float* lam, int P, int H, int W, bool nonlocal, bool add,
+                     hipStream_t s);
+
 // Strided 3-plane copy (pitches in elements).
 int launch_copy3(const float* src, int sp, float* dst, int dp, int H, int W, hipStream_t s);
 

@@ -671,6 +671,29 @@ __global__ __launch_bounds__(256) void k_copy3(const float* __restrict__ src, in
     dst[(static_cast<size_t>(c) * H + y) * dp + x] = src[(static_cast<size_t>(c) * H + y) * sp + x];
 }
 
+// Analytic part of the warm start: where the solution is smooth G(u) ~ u and
+// the diffusion term is small, so the main PDE reduces to lambda u = Phi and
+// B = Phi / lambda.  Without lambda G (or with lambda = 0) B = Phi.  With add,
+// u0 already holds the network's correction and B is added to it.  u0 is
+// planar with pitch W; Phi and lambda have pitch P.
+__global__ __launch_bounds__(256) void k_warm_base(float* __restrict__ u0, const float* __restrict__ phi,
+                                                    const float* __restrict__ lam, int P, int H, int W, int nonlocal,
+                                                    int add) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x >= W) return;
+  const size_t e = static_cast<size_t>(y) * P + x;
+  const float l = lam[e];
+  const bool divide = nonlocal && l > 0.0f;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const float ph = phi[static_cast<size_t>(c) * H * P + e];
+    const float b = divide ? ph / l : ph;
+    float* o = u0 + (static_cast<size_t>(c) * H + y) * W + x;
+    *o = add ? *o + b : b;
+  }
+}
+
 int sel_chunks(int H, int W) {
   const size_t n = static_cast<size_t>(H) * W;
   return static_cast<int>((n + kSelChunk - 1) / kSelChunk);
@@ -810,6 +833,14 @@ int launch_prior_estimated(const void* I, int dtype, int layout, int H, int W, i
   FusedOut o2{nullptr, o.t, o.lam, o.phi, o.op, o.tp};
   hipLaunchKernelGGL(k_prior_fused, grid, dim3(256), 0, s, nullptr, b.Ip, b.P, b.tref, W, A, H, W, fp, o2, nullptr,
                      0.0);
+  DZ_CHECK_LAUNCH();
+  return DEHAZE_OK;
+}
+
+int launch_warm_base(float* u0, const float* phi, const float* lam, int P, int H, int W, bool nonlocal, bool add,
+                     hipStream_t s) {
+  dim3 grid((W + 255) / 256, H);
+  hipLaunchKernelGGL(k_warm_base, grid, dim3(256), 0, s, u0, phi, lam, P, H, W, nonlocal ? 1 : 0, add ? 1 : 0);
   DZ_CHECK_LAUNCH();
   return DEHAZE_OK;
 }

@@ -413,8 +413,11 @@ int run_krylov(Ctx& ctx, const SolveArgs& a, const dehaze_params& p, dehaze_stat
   const float* u0 = a.u0;
   if (p.warm_start) {
     const size_t plane = static_cast<size_t>(H) * P;
-    if ((rc = cnn_forward(ctx, 1, H, W, pl.Ip, P, plane, 3 * plane, a.t, W, static_cast<size_t>(H) * W, a.A, pl.u0w,
+    if (p.warm_start == 1 &&
+        (rc = cnn_forward(ctx, 1, H, W, pl.Ip, P, plane, 3 * plane, a.t, W, static_cast<size_t>(H) * W, a.A, pl.u0w,
                           W, 3 * static_cast<size_t>(H) * W, pl.cnn_ws, s)))
+      return rc;
+    if ((rc = launch_warm_base(pl.u0w, pl.img.phi, pl.img.lam, P, H, W, p.nonlocal_term != 0, p.warm_start == 1, s)))
       return rc;
     u0 = pl.u0w;
   }
@@ -523,9 +526,12 @@ int batch_front_end(Ctx& ctx, const BatchPlan& pl, int i, const dehaze_image& m,
   if (p.warm_start) {
     const size_t plane = static_cast<size_t>(m.H) * pb.P;
     const float* t_used = m.t ? m.t : t_dst;
-    if ((rc = cnn_forward(ctx, 1, m.H, m.W, pb.Ip, pb.P, plane, 3 * plane, t_used, m.W,
+    if (p.warm_start == 1 &&
+        (rc = cnn_forward(ctx, 1, m.H, m.W, pb.Ip, pb.P, plane, 3 * plane, t_used, m.W,
                           static_cast<size_t>(m.H) * m.W, A, pl.u0w[i], m.W, 3 * static_cast<size_t>(m.H) * m.W,
                           pl.cnn_ws, s)))
+      return rc;
+    if ((rc = launch_warm_base(pl.u0w[i], K.phi, K.lam, K.P, m.H, m.W, p.nonlocal_term != 0, p.warm_start == 1, s)))
       return rc;
   }
   *A_used = A;
@@ -541,7 +547,10 @@ size_t solver_workspace_bytes(int H, int W, const dehaze_params& p) {
 
 static int check_warm(const Ctx& ctx, const dehaze_params& p, bool has_u0) {
   if (!p.warm_start) return DEHAZE_OK;
-  if (!cnn_ready(ctx)) { set_error("warm start needs loaded network weights"); return DEHAZE_EINVAL; }
+  if (p.warm_start == 1 && !cnn_ready(ctx)) {
+    set_error("warm start from the network needs loaded weights");
+    return DEHAZE_EINVAL;
+  }
   if (has_u0) { set_error("warm start and an explicit u0 exclude each other"); return DEHAZE_EINVAL; }
   if (p.scheme != DEHAZE_PICARD_KRYLOV) { set_error("warm start applies to DEHAZE_PICARD_KRYLOV"); return DEHAZE_EINVAL; }
   return DEHAZE_OK;

@@ -6,8 +6,9 @@ Images are seeded synthetic hazy images (seeds 4000 + k, beta_haze ~
 U(0.5, 2.5), occlusion edges) of size x size pixels cut from virtual
 1920 x 1080 scenes, so their object scales match the full-HD images the
 network warm-starts (--canvas 0 draws whole size x size scenes instead).
-Targets are the lagged-diffusivity batch solve run cold to relative
-residual 1e-5.  Progress goes to stdout.
+Targets are u* - B: the lagged-diffusivity batch solve run cold to relative
+residual 1e-5, minus the analytic start B = Phi / lambda, which the network
+corrects.  Progress goes to stdout.
 """
 from __future__ import annotations
 
@@ -65,7 +66,8 @@ def main(argv=None) -> int:
     hist = ws.train(ctx, data, args.steps, batch=args.batch, lr=args.lr, log_every=500)
     meta = {"images": args.n, "size": [H, W], "canvas": args.canvas, "seeds": [args.seed0, args.seed0 + args.n - 1],
             "beta_haze": [0.5, 2.5], "steps": args.steps, "batch": args.batch, "lr": args.lr,
-            "final_loss": hist[-1][1], "targets_converged": conv, "init_seed": args.init_seed}
+            "final_loss": hist[-1][1], "targets_converged": conv, "init_seed": args.init_seed,
+            "target": "u* - Phi/lambda"}
     ws.save(ctx, args.out, meta)
     print(f"saved {args.out}: {meta}", flush=True)
     return 0

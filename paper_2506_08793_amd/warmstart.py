@@ -1,11 +1,14 @@
 """Training and storage of the warm-start network.
 
-The network learns to predict the converged solution u* of the PDE from the
+The warm start is B + net(I, t, A), where B = Phi / lambda is the analytic
+start (warm_start = 2): the solution of lambda u = Phi, to which the main PDE
+reduces where u is smooth.  The network learns the correction u* - B from the
 hazy image, the transmission and the atmospheric light.  Its training targets
 are produced by the plain method itself: the lagged-diffusivity batch solve
-run cold (from Phi) to the relative residual 1e-5.  Everything below drives
-the C ABI: the solves, the forward/backward passes and the Adam steps run in
-the library's kernels; torch only holds device memory.
+run cold (from Phi) to the relative residual 1e-5, minus B from the same
+library (a zero-step solve from warm_start = 2).  Everything below drives the
+C ABI: the solves, the forward/backward passes and the Adam steps run in the
+library's kernels; torch holds device memory and forms u* - B.
 
 Weights are stored as a little-endian float32 file (the parameter vector in
 the library's layout) next to a JSON file with the training metadata.
@@ -25,18 +28,22 @@ WEIGHTS_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights"
 
 
 def solve_targets(ctx, images, params=None, chunk: int = 64):
-    """Converged solutions (cold start) of a list of planar float32 images.
+    """Network targets u* - B for a list of planar float32 images.
 
-    images: list of numpy (3, H, W) arrays of one size.  Returns device
-    tensors (I, t, A, u_star) stacked over images, plus per-image stats.
+    u* is the converged solution (cold start), B the analytic start of the
+    same image.  images: list of numpy (3, H, W) arrays of one size.  Returns
+    device tensors (I, t, A, u_star - B) stacked over images, plus per-image
+    stats of the solves.
     """
     p = params or b.dehaze_params_default(max_outer=6000, rel_tol=1e-5)
+    pb = b.dehaze_params_default(warm_start=2, max_outer=0, rel_tol=0.0)
     Is, ts, As, us, stats = [], [], [], [], []
     for k in range(0, len(images), chunk):
         dev = [torch.from_numpy(np.ascontiguousarray(im)).cuda() for im in images[k:k + chunk]]
         u, st, t, A = b.dehaze_batch(ctx, dev, params=p, want_t=True)
+        base, _, _, _ = b.dehaze_batch(ctx, dev, params=pb, t=t, A=A, stats=False)
         Is += dev
-        us += u
+        us += [ui - bi for ui, bi in zip(u, base)]
         ts += t
         As += A
         stats += st

@@ -124,13 +124,16 @@ def test_warm_started_solve_starts_from_prediction():
     img = synth.hazy_image(40, 52, 50, beta_haze=1.0)
     pr = o.prior(img["I"])
     t32, A32 = pr["t"].astype(np.float32), pr["A"].astype(np.float32)
-    u_pred = c.warm_start(img["I"], t32, A32, c.unflatten(w))
+    lam = o.adaptive_weight(t32.astype(np.float64))
+    phi = o.reconstruction(img["I"], t32, A32, o.DEFAULT.t0)
+    corr = c.warm_start(img["I"], t32, A32, c.unflatten(w))
+    u_pred = o.analytic_start(phi, lam) + corr
     say("warm-started solve 40x52")
     p0 = d.dehaze_params_default(warm_start=1, max_outer=0, rel_tol=0.0)
     u0, st0 = d.dehaze_solve(ctx(), dev(img["I"]), dev(t32), dev(A32), params=p0)
-    assert np.max(np.abs(host(u0) - u_pred)) <= 2e-2 * np.max(np.abs(u_pred))
-    lam = o.adaptive_weight(t32.astype(np.float64))
-    phi = o.reconstruction(img["I"], t32, A32, o.DEFAULT.t0)
+    # the start is B plus the network's correction; the bound is the
+    # network's (bf16 activations), taken relative to the correction
+    assert np.max(np.abs(host(u0) - u_pred)) <= 2e-2 * np.max(np.abs(corr)) + 1e-5 * np.max(np.abs(u_pred))
     _, rho_pred = o.residual(host(u0).astype(np.float64), phi, lam)
     assert abs(st0["rel_residual0"] - rho_pred) <= 1e-4 * rho_pred + 4e-6
     p = d.dehaze_params_default(warm_start=1, max_outer=3000, rel_tol=1e-5, check_every=16)
@@ -141,11 +144,44 @@ def test_warm_started_solve_starts_from_prediction():
         d.dehaze_solve(ctx(), dev(img["I"]), dev(t32), dev(A32), params=p, u0=dev(phi.astype(np.float32)))
 
 
+@pytest.mark.parametrize("flags", [{}, {"nonlocal_term": 0}, {"adaptive": 0}])
+def test_analytic_start_parity(flags):
+    # warm_start = 2 starts from B = Phi / lambda (Phi without the nonlocal
+    # term); a zero-step solve returns it, and three lagged-diffusivity steps
+    # from it follow the oracle's exact steps from the same start.
+    require_gpu()
+    import paper_2506_08793_amd as d
+    img = synth.hazy_image(45, 70, 51, beta_haze=1.0)
+    pr = o.prior(img["I"])
+    t32, A32 = pr["t"].astype(np.float32), pr["A"].astype(np.float32)
+    q = o.with_params(**{k: bool(v) for k, v in flags.items()})
+    lam = o.adaptive_weight(t32.astype(np.float64), q)
+    phi = o.reconstruction(img["I"], t32, A32, o.DEFAULT.t0)
+    B = o.analytic_start(phi, lam, q)
+    say(f"analytic start 45x70 {flags}")
+    p0 = d.dehaze_params_default(warm_start=2, max_outer=0, rel_tol=0.0, **flags)
+    u0, _ = d.dehaze_solve(ctx(), dev(img["I"]), dev(t32), dev(A32), params=p0)
+    # float32 Phi and lambda, one rounded division: a few float32 ulps of B
+    assert np.max(np.abs(host(u0) - B)) <= 4 * 2.0 ** -24 * np.max(np.abs(B))
+    if q.nonlocal_term:
+        # (without lambda G the operator has no zeroth-order term and the
+        # inner solves of a few steps are not tight enough to compare; the
+        # steps themselves are tested from other starts elsewhere)
+        p3 = d.dehaze_params_default(warm_start=2, max_outer=3, rel_tol=0.0, inner_rtol=1e-4, max_inner=200,
+                                     inner_refine=3, **flags)
+        u3, _ = d.dehaze_solve(ctx(), dev(img["I"]), dev(t32), dev(A32), params=p3)
+        ref = o.solve(phi, lam, "picard", q, steps=3, u0=host(u0).astype(np.float64))
+        assert np.max(np.abs(host(u3) - ref.u)) <= 1e-4 * max(1.0, np.max(np.abs(ref.u)))
+    with pytest.raises(d.DehazeError):
+        d.dehaze_solve(ctx(), dev(img["I"]), dev(t32), dev(A32), params=p0, u0=dev(phi.astype(np.float32)))
+
+
 def test_trained_network_gains_on_held_out_windows():
-    # The shipped network against the plain method on 256x256 windows of the
-    # distribution it was trained on (seeds it never saw): its prediction
-    # starts the lagged-diffusivity iteration at a smaller residual, and the
-    # batch reaches rho <= 1e-5 in fewer outer steps in total.
+    # The shipped network against the method without it, on 256x256 windows
+    # of the distribution it was trained on (seeds it never saw): its start
+    # B + correction lies at less than 0.6 of the distance of B alone from
+    # the converged solution (measured 0.41), and the batch reaches
+    # rho <= 1e-5 in fewer outer steps in total than from Phi.
     require_gpu()
     import time
     import torch
@@ -154,18 +190,21 @@ def test_trained_network_gains_on_held_out_windows():
     warmstart.load(ctx(), warmstart.default_weights_path())
     imgs = [dev(synth.hazy_window(256, 256, 9000 + k)["I"]) for k in range(8)]
     res = {}
-    for warm in (0, 1):
+    for warm in (0, 2, 1):
         p = d.dehaze_params_default(max_outer=4000, rel_tol=1e-5, warm_start=warm)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        _, st, _, _ = d.dehaze_batch(ctx(), imgs, params=p)
+        u, st, _, _ = d.dehaze_batch(ctx(), imgs, params=p)
         torch.cuda.synchronize()
-        res[warm] = (time.perf_counter() - t0, st)
-    for warm in (0, 1):
-        dt, st = res[warm]
-        say(f"  {'warm' if warm else 'cold'}: {dt:.3f} s, outer {[s['outer'] for s in st]}, "
-            f"rho0 mean {np.mean([s['rel_residual0'] for s in st]):.3f}")
+        u0, _, _, _ = d.dehaze_batch(ctx(), imgs, params=d.dehaze_params_default(max_outer=0, rel_tol=0.0,
+                                                                                  warm_start=warm), stats=False)
+        res[warm] = (time.perf_counter() - t0, st, u, u0)
+    ustar = res[0][2]
+    dist = {}
+    for warm in (0, 2, 1):
+        dt, st, _, u0 = res[warm]
+        dist[warm] = float(np.mean([np.mean(np.abs(host(a) - host(b))) for a, b in zip(u0, ustar)]))
+        say(f"  warm_start={warm}: {dt:.3f} s, outer {[s['outer'] for s in st]}, mean|u0 - u*| {dist[warm]:.3f}")
         assert all(s["converged"] for s in st)
-    cold, warm = res[0][1], res[1][1]
-    assert np.mean([s["rel_residual0"] for s in warm]) <= 0.7 * np.mean([s["rel_residual0"] for s in cold])
-    assert sum(s["outer"] for s in warm) < sum(s["outer"] for s in cold)
+    assert dist[1] <= 0.6 * dist[2]
+    assert sum(s["outer"] for s in res[1][1]) < sum(s["outer"] for s in res[0][1])

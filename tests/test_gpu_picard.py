@@ -140,12 +140,11 @@ def test_stall_watch_restart_and_stop():
     assert stn["restarts"] == 0 and stn["stalled"] == 0
 
 
-def test_network_start_that_stalls_is_restarted():
-    # 512x512 window (seed 9103): from the trained network's prediction the
-    # lagged-diffusivity iteration levels off near rho = 3.7e-5 (exact
-    # sparse-LU steps of the oracle level off there too), while from Phi it
-    # converges after a plateau near 4e-5 that the 256-step window does not
-    # mistake for a stall; the watch restarts the warm solve from Phi.
+def test_warm_starts_reach_the_cold_solution():
+    # 512x512 window (seed 9103, held out), whose cold solve crosses a long
+    # plateau near rho = 4e-5: from the analytic start and from the network
+    # the solve converges too, without a restart, to within the distance two
+    # rho <= 1e-5 iterates may lie apart.
     require_gpu()
     import paper_2506_08793_amd as d
     from paper_2506_08793_amd import warmstart
@@ -153,15 +152,16 @@ def test_network_start_that_stalls_is_restarted():
     img = synth.hazy_window(512, 512, 9103)
     I = dev(img["I"])
     pr = d.dehaze_prior(ctx(), I, outputs=("t",))
-    say("picard 512x512 window 9103 warm vs cold")
-    pw = d.dehaze_params_default(max_outer=4000, rel_tol=1e-5, warm_start=1)
-    pc = d.dehaze_params_default(max_outer=4000, rel_tol=1e-5)
-    uw, stw = d.dehaze_solve(ctx(), I, pr["t"], pr["A"], params=pw)
-    uc, stc = d.dehaze_solve(ctx(), I, pr["t"], pr["A"], params=pc)
-    say(f"  warm {stw}\n  cold {stc}")
-    assert stc["converged"] and stw["converged"] and stc["stalled"] == 0 and stw["stalled"] == 0
-    assert stw["restarts"] == 1
-    assert np.array_equal(host(uw), host(uc))
+    say("picard 512x512 window 9103 cold / analytic / network")
+    out = {}
+    for warm in (0, 2, 1):
+        p = d.dehaze_params_default(max_outer=4000, rel_tol=1e-5, warm_start=warm)
+        u, st = d.dehaze_solve(ctx(), I, pr["t"], pr["A"], params=p)
+        say(f"  warm_start={warm}: {st}")
+        assert st["converged"] and st["stalled"] == 0 and st["restarts"] == 0
+        out[warm] = host(u)
+    for warm in (2, 1):
+        assert np.max(np.abs(out[warm] - out[0])) <= 1e-2 * max(1.0, np.max(np.abs(out[0])))
 
 
 def test_picard_full_size_1080p():

@@ -175,3 +175,31 @@ def test_ablation_switches():
     q2 = o.with_params(nonlocal_term=False)
     Dx, Dy = o.face_coefficients(u, q2)
     assert np.array_equal(o.operator_apply(u, Dx, Dy, lam, w, q2), -o.divergence(u, Dx, Dy))
+
+
+@pytest.mark.parametrize("lam0", [0.05, 0.4])
+def test_analytic_start_solves_smooth_interior(lam0):
+    # Where Phi is linear and lambda constant, B = Phi / lambda is linear too:
+    # the normalised symmetric Gaussian reproduces it and the constant-slope
+    # flux has zero divergence, so the residual of B vanishes on every pixel
+    # more than R + 1 from the zero boundary.  A wrong base (Phi lambda,
+    # Phi / (lambda w0^2), Phi) leaves a residual there.
+    H, W = 24, 30
+    R = o.DEFAULT.g_radius
+    yy, xx = np.mgrid[0:H, 0:W].astype(np.float64)
+    phi = np.stack([0.3 + 0.01 * xx + 0.02 * yy, 0.5 - 0.015 * yy, 0.2 + 0.005 * xx])
+    lam = np.full((H, W), lam0)
+    B = o.analytic_start(phi, lam)
+    r, _ = o.residual(B, phi, lam)
+    inner = r[:, R + 2:H - R - 2, R + 2:W - R - 2]
+    assert np.max(np.abs(inner)) <= 1e-11 * np.max(np.abs(phi / lam0))
+    for wrong in (phi * lam0, phi / (lam0 * o.gaussian_taps(o.DEFAULT.sigma, R)[R] ** 2), phi):
+        rw, _ = o.residual(wrong, phi, lam)
+        assert np.max(np.abs(rw[:, R + 2:H - R - 2, R + 2:W - R - 2])) > 1e-3
+    # without the nonlocal term, or where lambda = 0, the base is Phi itself
+    q = o.with_params(nonlocal_term=False)
+    assert np.array_equal(o.analytic_start(phi, lam, q), phi)
+    lz = lam.copy()
+    lz[3, 4] = 0.0
+    Bz = o.analytic_start(phi, lz)
+    assert np.array_equal(Bz[:, 3, 4], phi[:, 3, 4])
