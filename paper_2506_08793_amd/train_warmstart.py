@@ -1,6 +1,8 @@
 """Train the warm-start network on converged solutions of the plain method.
 
     python -m paper_2506_08793_amd.train_warmstart --n 2048 --size 256 --steps 6000 --out <path>
+    python -m paper_2506_08793_amd.train_warmstart --n 256 --size 1080x1920 --canvas 0 --batch 2 \
+        --chunk 32 --seed0 8000 --steps 6000 --out <path>      (the shipped default)
 
 Images are seeded synthetic hazy images (seeds 4000 + k, beta_haze ~
 U(0.5, 2.5), occlusion edges) of size x size pixels cut from virtual
@@ -26,7 +28,7 @@ from . import warmstart as ws
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--n", type=int, default=2048)
-    ap.add_argument("--size", type=int, default=256)
+    ap.add_argument("--size", default="256", help="side of square images, or HxW")
     ap.add_argument("--steps", type=int, default=6000)
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--lr", type=float, default=2e-3)
@@ -34,12 +36,12 @@ def main(argv=None) -> int:
     ap.add_argument("--init-seed", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=256)
     ap.add_argument("--canvas", default="1080x1920", help="HxW of the virtual scene, or 0")
-    ap.add_argument("--out", default=ws.default_weights_path())
+    ap.add_argument("--out", required=True)
     args = ap.parse_args(argv)
     import synth  # seeded input generator (repository root)
 
     ctx = b.Context(0)
-    H = W = args.size
+    H, W = (int(v) for v in args.size.split("x")) if "x" in args.size else (int(args.size),) * 2
     t0 = time.time()
     imgs = []
     canvas = None if args.canvas in ("0", "") else tuple(int(v) for v in args.canvas.split("x"))
@@ -48,6 +50,8 @@ def main(argv=None) -> int:
             imgs.append(synth.hazy_window(H, W, args.seed0 + k, canvas=canvas)["I"])
         else:
             imgs.append(synth.hazy_image(H, W, args.seed0 + k, beta_haze=(0.5, 2.5), occlusion=True)["I"])
+        if (k + 1) % 64 == 0:
+            print(f"generated {k + 1}/{args.n} ({time.time() - t0:.1f} s)", flush=True)
     print(f"generated {args.n} images {H}x{W} in {time.time() - t0:.1f} s", flush=True)
     t0 = time.time()
     data, stats = None, []

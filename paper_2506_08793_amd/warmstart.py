@@ -92,4 +92,11 @@ def load(ctx, path: str) -> dict:
 
 
 def default_weights_path() -> str:
-    return os.path.join(WEIGHTS_DIR, "warmstart_256.f32")
+    """The shipped network for full-HD warm starts: trained on 256 whole
+    1920x1080 images (seeds 8000+).  weights_path(256) is the one trained on
+    2048 windows of 256x256 (seeds 4000+)."""
+    return weights_path(1080)
+
+
+def weights_path(size: int) -> str:
+    return os.path.join(WEIGHTS_DIR, f"warmstart_{size}.f32")

@@ -177,8 +177,8 @@ def test_analytic_start_parity(flags):
 
 
 def test_trained_network_gains_on_held_out_windows():
-    # The shipped network against the method without it, on 256x256 windows
-    # of the distribution it was trained on (seeds it never saw): its start
+    # The network trained on 256x256 windows against the method without it,
+    # on windows of that distribution (seeds it never saw): its start
     # B + correction lies at less than 0.6 of the distance of B alone from
     # the converged solution (measured 0.41), and the batch reaches
     # rho <= 1e-5 in fewer outer steps in total than from Phi.
@@ -187,7 +187,7 @@ def test_trained_network_gains_on_held_out_windows():
     import torch
     import paper_2506_08793_amd as d
     from paper_2506_08793_amd import warmstart
-    warmstart.load(ctx(), warmstart.default_weights_path())
+    warmstart.load(ctx(), warmstart.weights_path(256))
     imgs = [dev(synth.hazy_window(256, 256, 9000 + k)["I"]) for k in range(8)]
     res = {}
     for warm in (0, 2, 1):
