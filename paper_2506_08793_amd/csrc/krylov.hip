@@ -40,7 +40,24 @@ KConst make_kconst(const dehaze_params& p) {
 }
 
 int krylov_tiles(int H, int W) { return ((W + kKTX - 1) / kKTX) * ((H + kKTY - 1) / kKTY); }
-int krylov_units(int H, int W) { return 3 * ((W + kUOW - 1) / kUOW) * ((H + kUS - 1) / kUS); }
+// Taller strips cost less per row (fewer halo rows and partial sums) but give
+// fewer wavefronts; an image takes the tallest of 128, 64, 32 and 16 rows
+// that still gives it at least 768 wavefronts (three quarters of the 1024
+// SIMDs), else 16.  Timed on 1920x1080: 128 rows 7.6% faster than 32 (one
+// image), 4.9% (four); on 512x512 and 256x256 batches 128 rows are 35-76%
+// slower, since the last images of a batch to converge then run on few
+// wavefronts.
+int krylov_strip_rows(int H, int W) {
+  const int cols = (W + kUOW - 1) / kUOW;
+  for (int us = 128; us > 16; us /= 2)
+    if (3 * cols * ((H + us - 1) / us) >= 768) return us;
+  return 16;
+}
+
+int krylov_units(int H, int W) {
+  const int us = krylov_strip_rows(H, W);
+  return 3 * ((W + kUOW - 1) / kUOW) * ((H + us - 1) / us);
+}
 
 namespace {
 
@@ -63,6 +80,7 @@ KCarve carve(void* base, int H, int W, int tile0, int unit0) {
   m.ntiles = krylov_tiles(H, W);
   m.tile0 = tile0;
   m.ucols = (W + kUOW - 1) / kUOW;
+  m.us = krylov_strip_rows(H, W);
   m.nunits = krylov_units(H, W);
   m.unit0 = unit0;
   m.phi = cv.take<float>(3 * plane);
@@ -592,7 +610,7 @@ __global__ __launch_bounds__(NT) void k_red_b(const KImg* __restrict__ imgs, KSc
 // ------------------------------------------------------------ BiCGSTAB, strips
 // The operator kernels (a) and (b) for the radius-2 Gaussian as register-
 // resident strip walks: one wavefront per (image, channel, group of kUOW
-// columns, strip of kUS rows); lane = column with a 2-column halo on each
+// columns, strip of I.us rows); lane = column with a 2-column halo on each
 // side, horizontal neighbours by DPP shifts, vertical ones in 4-row windows.
 // Step r of the walk forms f = M^-1 q at input row r (q = p in (a), s in (b))
 // and applies the operator at row j = r - 2.  Loads go through buffer
@@ -621,7 +639,7 @@ __global__ __launch_bounds__(256) void k_bicg_strip(const KImg* __restrict__ img
   const bool xin = x >= 0 && x < I.W;
   const unsigned long long live = __builtin_amdgcn_ballot_w64(xin);
   const bool out_lane = lane >= 2 && lane < 2 + kUOW && xin;
-  const int y0 = strip * kUS, y1 = min(y0 + kUS, I.H);
+  const int y0 = strip * I.us, y1 = min(y0 + I.us, I.H);
   const int H = I.H, P = I.P;
   const unsigned pb = static_cast<unsigned>(H) * P * 4u, pby = static_cast<unsigned>(H + 1) * P * 4u;
   const size_t plane = static_cast<size_t>(H) * P, plane_y = static_cast<size_t>(H + 1) * P;

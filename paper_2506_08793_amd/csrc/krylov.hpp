@@ -2,7 +2,7 @@
 //
 // Every solve is watched: when over stall_window outer steps its lowest rho
 // has not fallen below half its value at the window's start, an image
-// started from a given iterate (the caller's u0 or the network's prediction)
+// started from a given iterate (the caller's u0 or a warm start)
 // restarts once from Phi; any other image of a tolerance-terminated solve
 // stops there, reported as stalled.  The fixed-point iteration of this
 // discretisation can level off short of the tolerance (the tangential
@@ -31,14 +31,14 @@ constexpr int kKTY = 16;   // tile height
 constexpr int kKPart = 4;  // doubles of partial sums per tile
 
 // Strip wavefronts of the BiCGSTAB operator kernels (Gaussian radius 2): one
-// wavefront per (channel, group of kUOW columns, strip of kUS rows).
-constexpr int kUS = 32;
+// wavefront per (channel, group of kUOW columns, strip of KImg::us rows).
 constexpr int kUOW = 60;
 
 struct KImg {
   int H, W, P;             // P: pitch of every plane, >= W + 1
   int tiles_x, ntiles, tile0;
   int ucols, nunits, unit0; // strip wavefronts: column groups, count, first global index
+  int us;                   // rows per strip wavefront
   const float* phi;        // 3 planes
   const float* lam;        // 1 plane
   double* u;               // 3 planes, the iterate
@@ -99,6 +99,8 @@ KConst make_kconst(const dehaze_params& p);
 size_t krylov_image_bytes(int H, int W);
 int krylov_tiles(int H, int W);
 int krylov_units(int H, int W);
+// Rows per strip wavefront for an H x W image (a function of the size only).
+int krylov_strip_rows(int H, int W);
 // Fills a descriptor whose planes live at `base` (krylov_image_bytes bytes,
 // 256-byte aligned); phi/lam are carved here too and returned through the
 // descriptor (the front end writes them).

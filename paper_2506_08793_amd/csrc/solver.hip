@@ -236,7 +236,7 @@ struct KrylovPlan {
   double* d_part = nullptr;
   int* d_unit_img = nullptr;
   double* d_upart = nullptr;
-  float* u0w = nullptr;   // network prediction (warm start), planar pitch W
+  float* u0w = nullptr;   // warm start B (+ the network's correction), planar pitch W
   char* cnn_ws = nullptr;
   size_t bytes = 0;
 };
@@ -452,7 +452,7 @@ struct BatchPlan {
   double* d_part = nullptr;
   int* d_unit_img = nullptr;
   double* d_upart = nullptr;
-  std::vector<float*> u0w;  // network predictions (warm start)
+  std::vector<float*> u0w;  // warm starts B (+ the network's correction)
   char* cnn_ws = nullptr;
   int ntiles = 0;
   int nunits = 0;
