@@ -36,27 +36,38 @@ KConst make_kconst(const dehaze_params& p) {
   c.nonlocal_term = p.nonlocal_term;
   c.edge_preserving = p.edge_preserving;
   c.stall_window = p.stall_window;
+  c.max_inner = p.max_inner;
+  c.max_outer = p.max_outer;
   return c;
 }
 
 int krylov_tiles(int H, int W) { return ((W + kKTX - 1) / kKTX) * ((H + kKTY - 1) / kKTY); }
-// Taller strips cost less per row (fewer halo rows and partial sums) but give
-// fewer wavefronts; an image takes the tallest of 128, 64, 32 and 16 rows
-// that still gives it at least 768 wavefronts (three quarters of the 1024
-// SIMDs), else 16.  Timed on 1920x1080: 128 rows 7.6% faster than 32 (one
-// image), 4.9% (four); on 512x512 and 256x256 batches 128 rows are 35-76%
-// slower, since the last images of a batch to converge then run on few
-// wavefronts.
-int krylov_strip_rows(int H, int W) {
-  const int cols = (W + kUOW - 1) / kUOW;
-  for (int us = 128; us > 16; us /= 2)
-    if (3 * cols * ((H + us - 1) / us) >= 768) return us;
-  return 16;
-}
+int krylov_units(int H, int W, int us) { return 3 * ((W + kUOW - 1) / kUOW) * ((H + us - 1) / us); }
 
-int krylov_units(int H, int W) {
-  const int us = krylov_strip_rows(H, W);
-  return 3 * ((W + kUOW - 1) / kUOW) * ((H + us - 1) / us);
+// Taller strips cost less per row (fewer halo rows and partial sums) but give
+// fewer wavefronts.  In a small launch each image takes the tallest of 128,
+// 64, 32 and 16 rows that still gives it at least 768 wavefronts (three
+// quarters of the 1024 SIMDs), else 16.  A launch that would carry more than
+// 32768 wavefronts at 32 rows runs 32 rows everywhere: there the wavefronts
+// queue in many rounds, and long ones lengthen the last round.  Timed against
+// 32 rows everywhere (batches solved to rho 1e-5): 1920x1080 x 1, 4, 8 (128 rows)
+// 8.0%, 4.8%, 4.8% faster, x 16 5.9% slower; 512x512 x 8 and 256x256 x 16
+// (16 rows) 3.2% and 8.1% faster.
+void krylov_strip_rows(int n, const int* H, const int* W, int* us) {
+  long long at32 = 0;
+  for (int i = 0; i < n; ++i) at32 += krylov_units(H[i], W[i], 32);
+  for (int i = 0; i < n; ++i) {
+    us[i] = 16;
+    if (at32 > 32768) {
+      us[i] = 32;
+      continue;
+    }
+    for (int r = 128; r > 16; r /= 2)
+      if (krylov_units(H[i], W[i], r) >= 768) {
+        us[i] = r;
+        break;
+      }
+  }
 }
 
 namespace {
@@ -66,7 +77,7 @@ struct KCarve {
   size_t bytes;
 };
 
-KCarve carve(void* base, int H, int W, int tile0, int unit0) {
+KCarve carve(void* base, int H, int W, int tile0, int unit0, int us) {
   KCarve k{};
   const int P = padded_pitch(W + 1);
   const size_t plane = static_cast<size_t>(H) * P;
@@ -80,8 +91,8 @@ KCarve carve(void* base, int H, int W, int tile0, int unit0) {
   m.ntiles = krylov_tiles(H, W);
   m.tile0 = tile0;
   m.ucols = (W + kUOW - 1) / kUOW;
-  m.us = krylov_strip_rows(H, W);
-  m.nunits = krylov_units(H, W);
+  m.us = us;
+  m.nunits = krylov_units(H, W, us);
   m.unit0 = unit0;
   m.phi = cv.take<float>(3 * plane);
   m.lam = cv.take<float>(plane);
@@ -172,6 +183,7 @@ __global__ __launch_bounds__(NT) void k_scal_reset(KScal* scal, int n) {
   if (i >= n) return;
   KScal z{};
   z.converged = 0;
+  z.inner_done = 1;  // no inner solve running: the next residual pass starts one
   scal[i] = z;
 }
 
@@ -229,7 +241,9 @@ __global__ __launch_bounds__(NT) void k_res(const KImg* __restrict__ imgs, KScal
   const int im = tile_img[g];
   const KImg I = imgs[im];
   KScal* sc = scal + im;
-  if (!final && sc->converged) return;
+  // a residual pass serves images between inner solves (the defect-correction
+  // pass of LINEAR follows a finished one too)
+  if (!final && (sc->converged || sc->exhausted || !sc->inner_done)) return;
   const TilePos tp = tile_pos(I, im, g);
   const int tid = threadIdx.x, tx = tid & (kKTX - 1), ty = tid / kKTX;
   const int gx = tp.x0 + tx;
@@ -337,7 +351,7 @@ __global__ __launch_bounds__(NT) void k_red_res(const KImg* __restrict__ imgs, K
   const int im = blockIdx.x;
   const KImg I = imgs[im];
   KScal* sc = scal + im;
-  if (!final && sc->converged) return;
+  if (!final && (sc->converged || sc->exhausted || !sc->inner_done)) return;
   double tot[3];
   image_sums<3>(I, part, tot);
   if (threadIdx.x != 0) return;
@@ -352,6 +366,13 @@ __global__ __launch_bounds__(NT) void k_red_res(const KImg* __restrict__ imgs, K
       sc->inner_this = 0;
     }
     sc->res_evals += 1;
+    // a pass beyond max_outer steps only records the residual (the final
+    // pass of the loop)
+    const bool over = !final && ++sc->passes > kc.max_outer;
+    if (over) {
+      sc->res_evals -= 1;
+      sc->exhausted = 1;
+    }
     const double rel = tot[1] > 0.0 ? sqrt(tot[0] / tot[1]) : sqrt(tot[0]);
     if (sc->res_evals == 1) sc->rel0 = rel;
     sc->rel = rel;
@@ -361,7 +382,7 @@ __global__ __launch_bounds__(NT) void k_red_res(const KImg* __restrict__ imgs, K
     } else if (kc.rel_tol > 0.0 && rel <= kc.rel_tol) {
       sc->converged = 1;
     }
-    if (!final && !sc->converged) {
+    if (!final && !sc->converged && !over) {
       if (sc->res_evals == 1 || sc->restart) {  // a new start: open a window
         sc->restart = 0;
         sc->best = sc->mark = rel;
@@ -394,9 +415,11 @@ __global__ __launch_bounds__(NT) void k_red_res(const KImg* __restrict__ imgs, K
     sc->beta = 0.0;
     sc->half_done = 0;
     sc->pass_inner = 0;
-    // no inner solve on a step that decided a restart: the next residual
-    // pass replaces the iterate
-    sc->inner_done = (tot[2] > 0.0 && isfinite(tot[2]) && !sc->restart) ? 0 : 1;
+    sc->it = 1;
+    // no inner solve on a step that decided a restart (the next residual pass
+    // replaces the iterate), nor once the iteration stops
+    sc->inner_done =
+        (tot[2] > 0.0 && isfinite(tot[2]) && !sc->restart && !sc->converged && !sc->exhausted) ? 0 : 1;
   }
 }
 
@@ -457,8 +480,7 @@ __device__ __forceinline__ void horiz_gauss(const float (&fs)[kKTY + 2 * HALO][k
 // (a) p = r + beta (p - omega v); v = L M^-1 p; sigma = (rhat, v); alpha = rho / sigma.
 template <int R>
 __global__ __launch_bounds__(NT) void k_bicg_a(const KImg* __restrict__ imgs, KScal* scal,
-                                                const int* __restrict__ tile_img, double* part, KConst kc,
-                                                int first, int par) {
+                                                const int* __restrict__ tile_img, double* part, KConst kc) {
   constexpr int HALO = R > 1 ? R : 1;
   constexpr int SX = kKTX + 2 * HALO, SY = kKTY + 2 * HALO;
   __shared__ float fs[SY][SX];
@@ -468,6 +490,7 @@ __global__ __launch_bounds__(NT) void k_bicg_a(const KImg* __restrict__ imgs, KS
   const KImg I = imgs[im];
   KScal* sc = scal + im;
   if (sc->converged || sc->inner_done) return;
+  const int first = sc->it == 1, par = sc->it & 1;
   const TilePos tp = tile_pos(I, im, g);
   const float beta = first ? 0.0f : static_cast<float>(sc->beta);
   const float omega = static_cast<float>(sc->omega);
@@ -532,8 +555,7 @@ __global__ __launch_bounds__(NT) void k_red_a(const KImg* __restrict__ imgs, KSc
 // (b) s = r - alpha v; t = L M^-1 s; omega = (t, s) / (t, t); ||s|| test.
 template <int R>
 __global__ __launch_bounds__(NT) void k_bicg_b(const KImg* __restrict__ imgs, KScal* scal,
-                                                const int* __restrict__ tile_img, double* part, KConst kc,
-                                                int first, int par) {
+                                                const int* __restrict__ tile_img, double* part, KConst kc) {
   constexpr int HALO = R > 1 ? R : 1;
   constexpr int SX = kKTX + 2 * HALO, SY = kKTY + 2 * HALO;
   __shared__ float fs[SY][SX];
@@ -543,6 +565,7 @@ __global__ __launch_bounds__(NT) void k_bicg_b(const KImg* __restrict__ imgs, KS
   const KImg I = imgs[im];
   KScal* sc = scal + im;
   if (sc->converged || sc->inner_done) return;
+  const int first = sc->it == 1, par = sc->it & 1;
   const TilePos tp = tile_pos(I, im, g);
   const float alpha = static_cast<float>(sc->alpha);
   const float* rs = first ? I.rhat : I.r;
@@ -620,7 +643,7 @@ __global__ __launch_bounds__(NT) void k_red_b(const KImg* __restrict__ imgs, KSc
 template <int MODE, bool FIRST>
 __global__ __launch_bounds__(256) void k_bicg_strip(const KImg* __restrict__ imgs, KScal* scal,
                                                      const int* __restrict__ unit_img, double* upart, KConst kc,
-                                                     int par, int nunits) {
+                                                     int nunits) {
 #pragma clang fp contract(off)
   constexpr int NA = MODE == 0 ? 2 : 1;  // partial sums
   constexpr int RING = 4, AHEAD = 3;
@@ -630,7 +653,10 @@ __global__ __launch_bounds__(256) void k_bicg_strip(const KImg* __restrict__ img
   const int im = __builtin_amdgcn_readfirstlane(unit_img[gw]);
   const KImg I = imgs[im];
   const KScal* sc = scal + im;
-  if (sc->converged || sc->inner_done) return;  // uniform per wavefront
+  // uniform per wavefront; the first iteration of an inner solve has its own
+  // instantiation
+  if (sc->converged || sc->inner_done || (sc->it == 1) != FIRST) return;
+  const int par = sc->it & 1;
   const int u = gw - I.unit0;
   const int c = u % 3, rest = u / 3;
   const int col = rest % I.ucols, strip = rest / I.ucols;
@@ -751,13 +777,13 @@ __global__ __launch_bounds__(256) void k_bicg_strip(const KImg* __restrict__ img
 
 // (c) x += alpha M^-1 p + omega M^-1 s; r = s - omega t; rho = (rhat, r); beta.
 __global__ __launch_bounds__(NT) void k_bicg_c(const KImg* __restrict__ imgs, KScal* scal,
-                                                const int* __restrict__ tile_img, double* part, KConst kc,
-                                                int first, int par) {
+                                                const int* __restrict__ tile_img, double* part, KConst kc) {
   const int g = blockIdx.x;
   const int im = tile_img[g];
   const KImg I = imgs[im];
   KScal* sc = scal + im;
   if (sc->converged || sc->inner_done) return;
+  const int first = sc->it == 1, par = sc->it & 1;
   const TilePos tp = tile_pos(I, im, g);
   const float alpha = static_cast<float>(sc->alpha);
   const float omega = static_cast<float>(sc->omega);
@@ -802,6 +828,8 @@ __global__ __launch_bounds__(NT) void k_red_c(const KImg* __restrict__ imgs, KSc
   if (threadIdx.x != 0) return;
   sc->inner_this += 1;
   sc->pass_inner += 1;
+  if (sc->it >= kc.max_inner) sc->inner_done = 1;
+  sc->it += 1;
   if (half) {
     sc->inner_done = 1;
   } else {
@@ -822,7 +850,8 @@ __global__ __launch_bounds__(NT) void k_update(const KImg* __restrict__ imgs, co
   const int im = tile_img[g];
   const KImg I = imgs[im];
   const KScal* sc = scal + im;
-  if (sc->converged || sc->pass_inner < 1) return;
+  // once per inner solve: after it ended, before the next residual pass
+  if (sc->converged || !sc->inner_done || sc->pass_inner < 1) return;
   const TilePos tp = tile_pos(I, im, g);
   const int tid = threadIdx.x, tx = tid & (kKTX - 1), ty = tid / kKTX;
   const int gx = tp.x0 + tx;
@@ -849,9 +878,11 @@ __global__ __launch_bounds__(NT) void k_update(const KImg* __restrict__ imgs, co
 
 }  // namespace
 
-size_t krylov_image_bytes(int H, int W) { return carve(nullptr, H, W, 0, 0).bytes; }
+size_t krylov_image_bytes(int H, int W) { return carve(nullptr, H, W, 0, 0, 32).bytes; }
 
-KImg krylov_carve(void* base, int H, int W, int tile0, int unit0) { return carve(base, H, W, tile0, unit0).img; }
+KImg krylov_carve(void* base, int H, int W, int tile0, int unit0, int us) {
+  return carve(base, H, W, tile0, unit0, us).img;
+}
 
 int krylov_init(const KrylovBatch& b, const KImg* h_imgs, const float* const* u0, hipStream_t s) {
   hipLaunchKernelGGL(k_scal_reset, dim3((b.nimg + NT - 1) / NT), dim3(NT), 0, s, b.d_scal, b.nimg);
@@ -903,34 +934,33 @@ int krylov_snapshot(const KrylovBatch& b, hipStream_t s) {
   return DEHAZE_OK;
 }
 
-int krylov_inner(const KrylovBatch& b, const KConst& c, int it, hipStream_t s) {
-  const int first = it == 1 ? 1 : 0;
-  const int par = it & 1;
+int krylov_inner(const KrylovBatch& b, const KConst& c, hipStream_t s) {
+  // one BiCGSTAB iteration for every image inside an inner solve; each image
+  // carries its own iteration count, so the first-iteration kernels run
+  // beside the others
   if (c.R == 2 && b.nunits > 0) {
     const dim3 ug((b.nunits + 3) / 4);
-    if (first)
-      hipLaunchKernelGGL((k_bicg_strip<0, true>), ug, dim3(256), 0, s, b.d_imgs, b.d_scal, b.d_unit_img, b.d_upart,
-                         c, par, b.nunits);
-    else
-      hipLaunchKernelGGL((k_bicg_strip<0, false>), ug, dim3(256), 0, s, b.d_imgs, b.d_scal, b.d_unit_img, b.d_upart,
-                         c, par, b.nunits);
+    hipLaunchKernelGGL((k_bicg_strip<0, true>), ug, dim3(256), 0, s, b.d_imgs, b.d_scal, b.d_unit_img, b.d_upart, c,
+                       b.nunits);
+    DZ_CHECK_LAUNCH();
+    hipLaunchKernelGGL((k_bicg_strip<0, false>), ug, dim3(256), 0, s, b.d_imgs, b.d_scal, b.d_unit_img, b.d_upart, c,
+                       b.nunits);
     DZ_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_red_a<true>, dim3(b.nimg), dim3(NT), 0, s, b.d_imgs, b.d_scal, b.d_upart);
     DZ_CHECK_LAUNCH();
-    if (first)
-      hipLaunchKernelGGL((k_bicg_strip<1, true>), ug, dim3(256), 0, s, b.d_imgs, b.d_scal, b.d_unit_img, b.d_upart,
-                         c, par, b.nunits);
-    else
-      hipLaunchKernelGGL((k_bicg_strip<1, false>), ug, dim3(256), 0, s, b.d_imgs, b.d_scal, b.d_unit_img, b.d_upart,
-                         c, par, b.nunits);
+    hipLaunchKernelGGL((k_bicg_strip<1, true>), ug, dim3(256), 0, s, b.d_imgs, b.d_scal, b.d_unit_img, b.d_upart, c,
+                       b.nunits);
+    DZ_CHECK_LAUNCH();
+    hipLaunchKernelGGL((k_bicg_strip<1, false>), ug, dim3(256), 0, s, b.d_imgs, b.d_scal, b.d_unit_img, b.d_upart, c,
+                       b.nunits);
     DZ_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_red_b<true>, dim3(b.nimg), dim3(NT), 0, s, b.d_imgs, b.d_scal, b.d_upart, c);
     DZ_CHECK_LAUNCH();
   } else {
 #define L_A(R) hipLaunchKernelGGL((k_bicg_a<R>), dim3(b.ntiles), dim3(NT), 0, s, b.d_imgs, b.d_scal, b.d_tile_img, \
-                                  b.d_part, c, first, par)
+                                  b.d_part, c)
 #define L_B(R) hipLaunchKernelGGL((k_bicg_b<R>), dim3(b.ntiles), dim3(NT), 0, s, b.d_imgs, b.d_scal, b.d_tile_img, \
-                                  b.d_part, c, first, par)
+                                  b.d_part, c)
     DZ_KRYLOV_DISPATCH(c.R, L_A)
     DZ_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_red_a<false>, dim3(b.nimg), dim3(NT), 0, s, b.d_imgs, b.d_scal, b.d_part);
@@ -942,8 +972,7 @@ int krylov_inner(const KrylovBatch& b, const KConst& c, int it, hipStream_t s) {
 #undef L_A
 #undef L_B
   }
-  hipLaunchKernelGGL(k_bicg_c, dim3(b.ntiles), dim3(NT), 0, s, b.d_imgs, b.d_scal, b.d_tile_img, b.d_part, c, first,
-                     par);
+  hipLaunchKernelGGL(k_bicg_c, dim3(b.ntiles), dim3(NT), 0, s, b.d_imgs, b.d_scal, b.d_tile_img, b.d_part, c);
   DZ_CHECK_LAUNCH();
   hipLaunchKernelGGL(k_red_c, dim3(b.nimg), dim3(NT), 0, s, b.d_imgs, b.d_scal, b.d_part, c);
   DZ_CHECK_LAUNCH();

@@ -77,6 +77,9 @@ struct KScal {
   int restarted;           // restarted once already
   int stalled;             // stopped: rho stopped falling (tolerance-terminated solves)
   double rel_out;          // rho of the iterate rounded to float32 (the returned u)
+  int it;                  // BiCGSTAB iteration of the current inner solve (1-based)
+  int passes;              // residual passes that may start a step (defect-correction passes excluded)
+  int exhausted;           // max_outer steps taken: done iterating
 };
 
 struct KConst {
@@ -92,19 +95,21 @@ struct KConst {
   int nonlocal_term;
   int edge_preserving;
   int stall_window;        // 0: never restart
+  int max_inner;
+  int max_outer;
 };
 KConst make_kconst(const dehaze_params& p);
 
 // Bytes of one image's planes (internal pitch) and its tile count.
 size_t krylov_image_bytes(int H, int W);
 int krylov_tiles(int H, int W);
-int krylov_units(int H, int W);
-// Rows per strip wavefront for an H x W image (a function of the size only).
-int krylov_strip_rows(int H, int W);
+int krylov_units(int H, int W, int us);
+// Rows per strip wavefront of each image of a launch of n images (us[i]).
+void krylov_strip_rows(int n, const int* H, const int* W, int* us);
 // Fills a descriptor whose planes live at `base` (krylov_image_bytes bytes,
 // 256-byte aligned); phi/lam are carved here too and returned through the
 // descriptor (the front end writes them).
-KImg krylov_carve(void* base, int H, int W, int tile0, int unit0);
+KImg krylov_carve(void* base, int H, int W, int tile0, int unit0, int us);
 
 struct KrylovBatch {
   const KImg* d_imgs;      // device copy of the descriptors
@@ -127,8 +132,10 @@ int krylov_residual(const KrylovBatch& b, const KConst& c, int final, hipStream_
 int krylov_linear_residual(const KrylovBatch& b, const KConst& c, hipStream_t s);
 // u_n := u for every image still iterating.
 int krylov_snapshot(const KrylovBatch& b, hipStream_t s);
-// One BiCGSTAB iteration (it = 1 for the first of an outer step).
-int krylov_inner(const KrylovBatch& b, const KConst& c, int it, hipStream_t s);
+// One BiCGSTAB iteration of every image inside an inner solve (each image
+// keeps its own iteration count; an inner solve ends at its tolerance or after
+// max_inner iterations).
+int krylov_inner(const KrylovBatch& b, const KConst& c, hipStream_t s);
 // u += delta.
 int krylov_update(const KrylovBatch& b, hipStream_t s);
 // u (float64) -> out (float, dense pitch W).

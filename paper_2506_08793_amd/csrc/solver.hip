@@ -245,9 +245,11 @@ KrylovPlan plan_krylov(void* ws, int H, int W, bool warm) {
   KrylovPlan pl;
   Carver cv(ws, ~size_t(0));
   char* arena = cv.take<char>(krylov_image_bytes(H, W));
-  pl.img = krylov_carve(arena, H, W, 0, 0);
+  int us = 32;
+  krylov_strip_rows(1, &H, &W, &us);
+  pl.img = krylov_carve(arena, H, W, 0, 0, us);
   const int nt = krylov_tiles(H, W);
-  const int nu = krylov_units(H, W);
+  const int nu = pl.img.nunits;
   pl.Ip = cv.take<float>(3 * static_cast<size_t>(H) * pl.img.P);
   pl.d_imgs = cv.take<KImg>(1);
   pl.d_scal = cv.take<KScal>(1);
@@ -282,7 +284,8 @@ void fill_stats(const KScal& k, dehaze_stats* st) {
   st->stalled = k.stalled;
 }
 
-// One lagged-diffusivity step for every image still iterating.
+// With defect-correction passes (inner_refine > 0): one lagged-diffusivity
+// step for every image still iterating, each pass max_inner iterations long.
 int outer_step(const KrylovBatch& b, const KConst& kc, const dehaze_params& p, hipStream_t s) {
   int rc;
   if ((rc = krylov_residual(b, kc, 0, s))) return rc;
@@ -290,11 +293,26 @@ int outer_step(const KrylovBatch& b, const KConst& kc, const dehaze_params& p, h
   for (int pass = 0; pass <= p.inner_refine; ++pass) {
     if (pass > 0 && (rc = krylov_linear_residual(b, kc, s))) return rc;
     for (int it = 1; it <= p.max_inner; ++it)
-      if ((rc = krylov_inner(b, kc, it, s))) return rc;
+      if ((rc = krylov_inner(b, kc, s))) return rc;
     if ((rc = krylov_update(b, s))) return rc;
   }
   return DEHAZE_OK;
 }
+
+// Without them (the default): one tick.  Images between inner solves get
+// their residual pass (and start the next inner solve), images inside one get
+// a BiCGSTAB iteration, and images whose inner solve just ended apply the
+// correction.  Every image advances at its own pace, so a replayed group of
+// ticks holds no iterations that only wait for the slowest inner solve.
+int tick_step(const KrylovBatch& b, const KConst& kc, hipStream_t s) {
+  int rc;
+  if ((rc = krylov_residual(b, kc, 0, s))) return rc;
+  if ((rc = krylov_inner(b, kc, s))) return rc;
+  return krylov_update(b, s);
+}
+
+// Ticks per captured graph.
+constexpr int kTicks = 64;
 
 }  // namespace
 
@@ -332,7 +350,8 @@ int graph_for(Ctx& ctx, const KrylovBatch& b, const KConst& kc, int steps, const
   if (!g.cap) DZ_HIP(hipStreamCreateWithFlags(&g.cap, hipStreamNonBlocking));
   DZ_HIP(hipStreamBeginCapture(g.cap, hipStreamCaptureModeThreadLocal));
   int rc = DEHAZE_OK;
-  for (int i = 0; i < steps && rc == DEHAZE_OK; ++i) rc = outer_step(b, kc, p, g.cap);
+  for (int i = 0; i < steps && rc == DEHAZE_OK; ++i)
+    rc = p.inner_refine > 0 ? outer_step(b, kc, p, g.cap) : tick_step(b, kc, g.cap);
   hipGraph_t graph = nullptr;
   const hipError_t e = hipStreamEndCapture(g.cap, &graph);
   if (rc) {
@@ -365,24 +384,39 @@ int graph_for(Ctx& ctx, const KrylovBatch& b, const KConst& kc, int steps, const
 int krylov_loop(Ctx& ctx, const KrylovBatch& b, const dehaze_params& p, KScal* h, bool need_scalars,
                 hipStream_t s) {
   const KConst kc = make_kconst(p);
-  const int per = std::max(1, std::min(p.check_every, p.max_outer));
-  hipGraphExec_t exec = nullptr;
   int rc;
-  if (p.max_outer >= per && (rc = graph_for(ctx, b, kc, per, p, &exec))) return rc;
-  int done = 0;
-  while (done < p.max_outer) {
-    const int k = std::min(per, p.max_outer - done);
-    if (k == per && exec) {
-      DZ_HIP(hipGraphLaunch(exec, s));
-    } else {
-      for (int i = 0; i < k; ++i)
-        if ((rc = outer_step(b, kc, p, s))) return rc;
+  if (p.inner_refine > 0) {
+    const int per = std::max(1, std::min(p.check_every, p.max_outer));
+    hipGraphExec_t exec = nullptr;
+    if (p.max_outer >= per && (rc = graph_for(ctx, b, kc, per, p, &exec))) return rc;
+    int done = 0;
+    while (done < p.max_outer) {
+      const int k = std::min(per, p.max_outer - done);
+      if (k == per && exec) {
+        DZ_HIP(hipGraphLaunch(exec, s));
+      } else {
+        for (int i = 0; i < k; ++i)
+          if ((rc = outer_step(b, kc, p, s))) return rc;
+      }
+      done += k;
+      if (p.rel_tol > 0.0) {
+        if ((rc = read_scalars(b, h, s))) return rc;
+        bool all = true;
+        for (int i = 0; i < b.nimg; ++i) all = all && h[i].converged;
+        if (all) break;
+      }
     }
-    done += k;
-    if (p.rel_tol > 0.0) {
+  } else {
+    // groups of ticks until every image has converged, stopped or taken
+    // max_outer steps; a step takes at most max_inner ticks
+    hipGraphExec_t exec = nullptr;
+    if ((rc = graph_for(ctx, b, kc, kTicks, p, &exec))) return rc;
+    const long long cap = (static_cast<long long>(p.max_outer) + 1) * std::max(1, p.max_inner) + 2;
+    for (long long ticks = 0; ticks < cap; ticks += kTicks) {
+      DZ_HIP(hipGraphLaunch(exec, s));
       if ((rc = read_scalars(b, h, s))) return rc;
       bool all = true;
-      for (int i = 0; i < b.nimg; ++i) all = all && h[i].converged;
+      for (int i = 0; i < b.nimg; ++i) all = all && (h[i].converged || h[i].exhausted);
       if (all) break;
     }
   }
@@ -471,10 +505,16 @@ BatchPlan plan_batch(void* ws, int n, const dehaze_image* im, const dehaze_param
   }
   pl.prior_ws = cv.take<char>(prior_max);
   if (warm) pl.cnn_ws = cv.take<char>(cnn_max);
+  std::vector<int> hs(n), wsz(n), us(n);
+  for (int i = 0; i < n; ++i) {
+    hs[i] = im[i].H;
+    wsz[i] = im[i].W;
+  }
+  krylov_strip_rows(n, hs.data(), wsz.data(), us.data());
   int tile0 = 0, unit0 = 0;
   for (int i = 0; i < n; ++i) {
     char* arena = cv.take<char>(krylov_image_bytes(im[i].H, im[i].W));
-    pl.imgs.push_back(krylov_carve(arena, im[i].H, im[i].W, tile0, unit0));
+    pl.imgs.push_back(krylov_carve(arena, im[i].H, im[i].W, tile0, unit0, us[i]));
     tile0 += pl.imgs.back().ntiles;
     unit0 += pl.imgs.back().nunits;
     const bool need_t = !im[i].t && !im[i].t_out;
