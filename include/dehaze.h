@@ -137,7 +137,7 @@ typedef struct dehaze_stats {
 typedef struct dehaze_ctx dehaze_ctx;
 
 /* Fills *p with the defaults listed above (scheme = DEHAZE_PICARD_KRYLOV,
-   max_outer = 5000, max_inner = 64, rel_tol = 1e-5, inner_rtol = 0.2,
+   max_outer = 5000, max_inner = 128, rel_tol = 1e-5, inner_rtol = 0.2,
    check_every = 16, inner_refine = 0, stall_window = 256).  Returns DEHAZE_EINVAL for NULL. */
 int dehaze_params_default(dehaze_params* p);
 

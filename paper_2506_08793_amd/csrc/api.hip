@@ -119,7 +119,7 @@ int dehaze_params_default(dehaze_params* p) {
   p->inner_rtol = 0.2;
   p->scheme = DEHAZE_PICARD_KRYLOV;
   p->max_outer = 5000;
-  p->max_inner = 64;
+  p->max_inner = 128;
   p->check_every = 16;
   p->atm_divisor = 1000;
   p->warm_start = 0;
