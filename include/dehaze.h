@@ -82,7 +82,8 @@ typedef struct dehaze_params {
   int32_t scheme;           /* DEHAZE_PAPER_EXPLICIT, DEHAZE_JACOBI, DEHAZE_PICARD_KRYLOV */
   int32_t max_outer;        /* sweeps (explicit, Jacobi) or lagged-diffusivity steps */
   int32_t max_inner;        /* BiCGSTAB iterations per lagged-diffusivity step */
-  int32_t check_every;      /* residual test every this many outer steps (>= 1) */
+  int32_t check_every;      /* with inner_refine > 0: outer steps per captured graph, after which the host
+                               reads the stopping flags (>= 1); the default loop ignores it */
   int32_t atm_divisor;      /* A from the top max(1, HW / atm_divisor) dark-channel pixels */
   int32_t warm_start;       /* starting iterate of the lagged-diffusivity solve (u0 must then be NULL):
                                0 = Phi (or u0); 2 = B = Phi / lambda, the solution of lambda u = Phi,
@@ -188,12 +189,14 @@ int dehaze_prior(dehaze_ctx* ctx, const void* I, int dtype, int layout, int H, i
  *   DEHAZE_PAPER_EXPLICIT, DEHAZE_JACOBI: p->max_outer sweeps, each one pass
  *     of the face-coefficient recompute and the update (Appendix A-1).
  *   DEHAZE_PICARD_KRYLOV: lagged-diffusivity steps; the residual of the
- *     current iterate is formed in float64 from a float32 hi/lo pair, each
- *     correction L_{D(u_n)} delta = r_n is solved by BiCGSTAB in float32.
- * With rel_tol > 0 the solve stops once rho <= rel_tol (tested every
- * check_every outer steps) and returns DEHAZE_ENOTCONV if max_outer passes
- * first.  `stats` (host, nullable) is filled; a non-NULL stats, or
- * rel_tol > 0, makes the call synchronise `stream`.
+ *     current iterate is formed in float64 from the float64 iterate, each
+ *     correction L_{D(u_n)} delta = r_n is solved by BiCGSTAB in float32
+ *     (to inner_rtol, at most max_inner iterations).
+ * With rel_tol > 0 the solve stops once rho <= rel_tol (tested on the device
+ * after every step) and returns DEHAZE_ENOTCONV if max_outer passes first.
+ * `stats` (host, nullable) is filled.  The sweep schemes synchronise
+ * `stream` when stats is non-NULL or rel_tol > 0; DEHAZE_PICARD_KRYLOV always
+ * does (the host reads the per-image state between graph replays).
  * u is not clipped: the solution of the PDE exceeds the [0, 1] range. */
 size_t dehaze_solve_workspace_size(int H, int W, const dehaze_params* p);
 int dehaze_solve(dehaze_ctx* ctx, const void* I, int dtype, int layout, int H, int W, int pitch,
@@ -204,13 +207,16 @@ int dehaze_solve(dehaze_ctx* ctx, const void* I, int dtype, int layout, int H, i
  * Many images of uneven size solved together by the lagged-diffusivity
  * scheme (DEHAZE_PICARD_KRYLOV only): every kernel launch covers the tiles of
  * all images still iterating, the per-image reductions and stopping tests run
- * on the device, and groups of check_every outer steps are captured once in a
- * HIP graph and replayed until every image reaches rel_tol (or max_outer).
+ * on the device, and groups of 64 ticks are captured once in a HIP graph and
+ * replayed until every image reaches rel_tol (or max_outer, or stalls).  In a
+ * tick each image does the next thing it needs (the residual pass that
+ * starts a step, one BiCGSTAB iteration, or the update that ends the step),
+ * at its own pace.  With inner_refine > 0, groups of check_every outer steps
+ * of max_inner iterations per pass are captured instead.
  * Per image, t and A are taken as given or, when NULL, estimated by the
  * front end of dehaze_prior (Section II-D); lambda(t) and Phi follow
- * (Sections II-A, II-D).  The call synchronises `stream` when rel_tol > 0
- * or stats is non-NULL.  stats (host, n entries, nullable) receives each
- * image's counts, residuals, A and status.  Returns DEHAZE_OK, or the worst
+ * (Sections II-A, II-D).  The call synchronises `stream`.  stats (host, n
+ * entries, nullable) receives each image's counts, residuals, A and status.  Returns DEHAZE_OK, or the worst
  * per-image status (DEHAZE_ENONFINITE before DEHAZE_ENOTCONV), or an error.
  * The context keeps the captured graph for reuse by a later call with the
  * same workspace, batch layout and parameters. */

@@ -106,3 +106,25 @@ def test_batch_rejects_bad_arguments():
         d.dehaze_batch(ctx(), [dev(arrs[0])], params=d.dehaze_params_default(scheme=d.JACOBI))
     with pytest.raises(d.DehazeError):
         d.dehaze_batch(ctx(), [dev(arrs[0])], params=d.dehaze_params_default(inner_refine=-1))
+
+
+@pytest.mark.parametrize("warm", [0, 2])
+def test_batch_images_progress_independently(warm):
+    # Default settings (tick loop): each image keeps its own BiCGSTAB
+    # iteration count, so an image of a batch goes through exactly the steps
+    # it goes through alone, whatever the other images need.  Sizes chosen so
+    # that the images differ in outer steps and iterations per step.
+    require_gpu()
+    import paper_2506_08793_amd as d
+    sizes = [(96, 128), (40, 31), (200, 150), (1, 1)]
+    arrs, _ = _images(sizes, 800)
+    p = d.dehaze_params_default(max_outer=3000, rel_tol=1e-5, warm_start=warm)
+    say(f"batch vs single, default settings, warm_start={warm}")
+    us, st, _, _ = d.dehaze_batch(ctx(), [dev(a) for a in arrs], params=p)
+    say(f"  outer {[s['outer'] for s in st]} inner {[s['inner'] for s in st]}")
+    assert len({s["outer"] for s in st}) > 1
+    for k, a in enumerate(arrs):
+        u1, st1, _, _ = d.dehaze_batch(ctx(), [dev(a)], params=p)
+        assert np.array_equal(host(u1[0]), host(us[k])), k
+        for key in ("outer", "inner", "applications", "rel_residual", "rel_residual0", "converged", "restarts"):
+            assert st1[0][key] == st[k][key], (k, key)
