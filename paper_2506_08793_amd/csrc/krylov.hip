@@ -789,26 +789,47 @@ __global__ __launch_bounds__(NT) void k_bicg_c(const KImg* __restrict__ imgs, KS
   const float omega = static_cast<float>(sc->omega);
   const int half = sc->half_done;
   const float* pn = pick(I.p, par);
-  const int tid = threadIdx.x, tx = tid & (kKTX - 1), ty = tid / kKTX;
-  const int gx = tp.x0 + tx;
+  // thread: 4 adjacent pixels of one row (16-byte accesses; rows start on
+  // 256-byte boundaries and the pitch holds every aligned group that starts
+  // inside the image)
+  const int ly = threadIdx.x >> 4, lx = (threadIdx.x & 15) * 4;
+  const int gy = tp.y0 + ly, gx = tp.x0 + lx;
   const size_t plane = static_cast<size_t>(I.H) * I.P;
   double acc[2] = {0.0, 0.0};  // (rhat, r), (r, r)
-  for (int c = 0; c < 3; ++c) {
-    for (int k = 0; k < kPixPerThread; ++k) {
-      const int gy = tp.y0 + ty + 4 * k;
-      if (gx < I.W && gy < I.H) {
-        const size_t e = c * plane + static_cast<size_t>(gy) * I.P + gx;
-        const float id = I.invd[e];
-        const float xo = first ? 0.0f : I.x[e];
-        if (half) {
-          I.x[e] = xo + alpha * (id * pn[e]);
-        } else {
-          const float sv = I.s[e];
-          I.x[e] = xo + alpha * (id * pn[e]) + omega * (id * sv);
-          const float rn = sv - omega * I.t[e];
-          I.r[e] = rn;
-          acc[0] += static_cast<double>(I.rhat[e]) * rn;
-          acc[1] += static_cast<double>(rn) * rn;
+  if (gy < I.H && gx < I.W) {
+    const int nv = min(4, I.W - gx);  // pixels inside the image
+    auto ld4 = [](const float* q) { return *reinterpret_cast<const float4*>(q); };
+    for (int c = 0; c < 3; ++c) {
+      const size_t e = c * plane + static_cast<size_t>(gy) * I.P + gx;
+      const float4 id4 = ld4(I.invd + e), p4 = ld4(pn + e);
+      const float4 x4 = first ? make_float4(0.0f, 0.0f, 0.0f, 0.0f) : ld4(I.x + e);
+      const float id[4] = {id4.x, id4.y, id4.z, id4.w}, pv[4] = {p4.x, p4.y, p4.z, p4.w};
+      const float xo[4] = {x4.x, x4.y, x4.z, x4.w};
+      float xn[4], rn[4];
+      if (half) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) xn[k] = xo[k] + alpha * (id[k] * pv[k]);
+      } else {
+        const float4 s4 = ld4(I.s + e), t4 = ld4(I.t + e), h4 = ld4(I.rhat + e);
+        const float sv[4] = {s4.x, s4.y, s4.z, s4.w}, tv[4] = {t4.x, t4.y, t4.z, t4.w};
+        const float hv[4] = {h4.x, h4.y, h4.z, h4.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          xn[k] = xo[k] + alpha * (id[k] * pv[k]) + omega * (id[k] * sv[k]);
+          rn[k] = sv[k] - omega * tv[k];
+          if (k < nv) {
+            acc[0] += static_cast<double>(hv[k]) * rn[k];
+            acc[1] += static_cast<double>(rn[k]) * rn[k];
+          }
+        }
+      }
+      if (nv == 4) {
+        *reinterpret_cast<float4*>(I.x + e) = make_float4(xn[0], xn[1], xn[2], xn[3]);
+        if (!half) *reinterpret_cast<float4*>(I.r + e) = make_float4(rn[0], rn[1], rn[2], rn[3]);
+      } else {
+        for (int k = 0; k < nv; ++k) {
+          I.x[e + k] = xn[k];
+          if (!half) I.r[e + k] = rn[k];
         }
       }
     }
