@@ -658,8 +658,10 @@ __global__ __launch_bounds__(256) void k_bicg_strip(const KImg* __restrict__ img
   if (sc->converged || sc->inner_done || (sc->it == 1) != FIRST) return;
   const int par = sc->it & 1;
   const int u = gw - I.unit0;
-  const int c = u % 3, rest = u / 3;
-  const int col = rest % I.ucols, strip = rest / I.ucols;
+  // column group fastest: the four wavefronts of a workgroup (one XCD, one
+  // L2) take adjacent column groups and share the cache lines between them
+  const int col = u % I.ucols, rest = u / I.ucols;
+  const int c = rest % 3, strip = rest / 3;
   const int lane = threadIdx.x & 63;
   const int x = col * kUOW - 2 + lane;
   const bool xin = x >= 0 && x < I.W;
