@@ -23,6 +23,24 @@ def test_gaussian_taps_properties():
         assert abs(w[3] / w[2] - np.exp(-1.0 / (2 * sigma * sigma))) < 1e-15
 
 
+def test_gaussian_taps_literal_values():
+    # Section II-C's kernel exp(-a^2 / 2 sigma^2) on a = -2..2 (Appendix A-2's
+    # 5x5 window), taps scaled to sum 1.  The numbers below were evaluated in
+    # 40-digit decimal arithmetic, independently of numpy's exp, at the
+    # workloads' sigma = 1.5 and the paper's sigma = 2.0; every tap is pinned,
+    # so a wrong exponent (|a| for a^2, a missing factor 2) fails on the outer
+    # taps even where the sum and the symmetry still hold.
+    want = {
+        1.5: [0.12007838424321348, 0.23388075658535030, 0.29208171834287245,
+              0.23388075658535030, 0.12007838424321348],
+        2.0: [0.15246914402033735, 0.22184129554377692, 0.25137912087177145,
+              0.22184129554377692, 0.15246914402033735],
+    }
+    for sigma, w_lit in want.items():
+        w = o.gaussian_taps(sigma, 2)
+        assert np.max(np.abs(w - np.array(w_lit))) <= 2e-16, (sigma, w)
+
+
 def test_gaussian_delta_response_and_library():
     w = o.gaussian_taps(1.5, 2)
     d = np.zeros((11, 13))
@@ -64,6 +82,27 @@ def test_face_gradients_by_hand():
     assert gny[0, 0, 2] == u[0, 0, 2] and gty[0, 0, 2] == 0.0
     # y-face between rows 0 and 1 at column 0: tangential (u(1,0) - 0)/2
     assert gny[0, 1, 0] == 4.0 and gty[0, 1, 0] == u[0, 0, 1] / 2
+
+
+def test_diffusivity_literal_values():
+    # Section II-B: D = 1 / (|grad u| + eps) with eps = 1e-3 (Section IV-B) and
+    # |grad u| the Euclidean norm of (normal, tangential) differences.  Values
+    # worked by hand: |(3, 4)| = 5, |(5, 12)| = 13, |(0.6, 0.8)| = 1.  A
+    # doubled eps, an l1 norm or a squared norm each miss these.
+    gn = np.array([3.0, 5.0, 0.6, 0.0, 1.0, -3.0])
+    gt = np.array([4.0, 12.0, 0.8, 0.0, 0.0, -4.0])
+    want = np.array([0.19996000799840032, 0.076917160218444735, 0.99900099900099900, 1000.0,
+                     0.99900099900099900, 0.19996000799840032])
+    D = o.diffusivity(gn, gt, 1e-3)
+    assert np.max(np.abs(D - want) / want) <= 4e-16, D
+    assert D[3] == 1000.0                                   # flat: D = 1 / eps exactly
+    assert np.array_equal(o.diffusivity(gn, gt, 1e-3, edge_preserving=False), np.ones(6))
+    # the face coefficients of a field whose face differences are these values
+    u = np.zeros((1, 3, 3))
+    u[0, 1, 1] = 3.0                  # x-face left of (1, 1): normal 3, tangential (u(0,2) - u(0,0)) / 2
+    u[0, 2, 0], u[0, 0, 0] = 8.0, 0.0
+    Dx, _ = o.face_coefficients(u)
+    assert abs(Dx[0, 1, 1] - 0.19996000799840032) <= 1e-16
 
 
 def test_diffusivity_assumption_1():
