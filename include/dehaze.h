@@ -288,6 +288,26 @@ int dehaze_residual(dehaze_ctx* ctx, const float* u, const float* phi, const flo
                     int H, int W, const dehaze_params* p, float* r, double* rho,
                     void* ws, size_t ws_bytes, void* stream);
 
+/* ------------------------------------------------------------ allocation-free residual
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Computes
+ * what dehaze_residual computes, with the same kernels, but takes no
+ * workspace, allocates nothing and does not synchronise: its per-block
+ * partial sums live in a library-owned device array of 256 bytes + 16 bytes
+ * per block (1 MiB + 256 bytes), one per GPU, held until the process ends,
+ * and rho is written to device memory.
+ *   u, phi, lam, H, W, p, r   as in dehaze_residual (r nullable)
+ *   rho    ONE DEVICE double receiving ||Phi - L_{D(u)} u|| / ||Phi||; it is
+ *          NaN or Inf when the residual is not finite (no host-side check)
+ * Limit: ceil(W / 64) * ceil(H / 16) <= DEHAZE_NOALLOC_MAX_BLOCKS (e.g. 8192
+ * x 8192); larger images return DEHAZE_EINVAL.  Every call on one GPU shares
+ * that GPU's array and leaves its own sums there: calls that overlap on one
+ * GPU (different streams, threads or contexts) race, so the caller must
+ * order them.  Errors: EINVAL (NULL pointer, size, parameters), EHIP. */
+#define DEHAZE_NOALLOC_MAX_BLOCKS 65536
+int dehaze_residual_noalloc(dehaze_ctx* ctx, const float* u, const float* phi, const float* lam,
+                            int H, int W, const dehaze_params* p, float* r, double* rho, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -113,6 +113,8 @@ _SIGS = {
     "dehaze_residual_workspace_size": (c_size_t, [c_int, c_int, _P]),
     "dehaze_residual": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, _P, c_void_p,
                                 POINTER(c_double), c_void_p, c_size_t, c_void_p]),
+    "dehaze_residual_noalloc": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, _P, c_void_p,
+                                        c_void_p, c_void_p]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _fn = getattr(_lib, _name)
@@ -255,6 +257,22 @@ def dehaze_residual(ctx: Context, u: torch.Tensor, phi: torch.Tensor, lam: torch
     _check(_lib.dehaze_residual(ctx.handle, u.data_ptr(), phi.data_ptr(), lam.data_ptr(), H, W, ctypes.byref(p),
                                 _ptr(r), ctypes.byref(rho), ws.data_ptr(), ws.numel(), _stream()))
     return rho.value, r
+
+
+def dehaze_residual_noalloc(ctx: Context, u: torch.Tensor, phi: torch.Tensor, lam: torch.Tensor,
+                            rho: torch.Tensor, params: Params = None, r: torch.Tensor = None) -> None:
+    """Allocation-free rho into the one-element float64 device tensor `rho`
+    (and Phi - L u into `r` when given); enqueued on the current stream, no
+    synchronisation.  The caller provides every output."""
+    p = params or dehaze_params_default()
+    _, H, W = u.shape
+    for tens in (u, phi, lam) + (() if r is None else (r,)):
+        if not (tens.is_cuda and tens.is_contiguous() and tens.dtype == torch.float32):
+            raise ValueError("u, phi, lam and r must be contiguous float32 device tensors")
+    if not (rho.is_cuda and rho.dtype == torch.float64 and rho.numel() >= 1):
+        raise ValueError("rho must be a float64 device tensor")
+    _check(_lib.dehaze_residual_noalloc(ctx.handle, u.data_ptr(), phi.data_ptr(), lam.data_ptr(), H, W,
+                                        ctypes.byref(p), _ptr(r), rho.data_ptr(), _stream()))
 
 
 def dehaze_batch(ctx: Context, images, params: Params = None, layout: str = "CHW", t=None, A=None, u0=None,

@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -78,6 +79,46 @@ int check_image(const void* I, int dtype, int layout, int H, int W, int pitch) {
   if (dtype != DEHAZE_U8 && dtype != DEHAZE_F32) { set_error("unknown dtype %d", dtype); return DEHAZE_EINVAL; }
   if (layout != DEHAZE_HWC && layout != DEHAZE_CHW) { set_error("unknown layout %d", layout); return DEHAZE_EINVAL; }
   return DEHAZE_OK;
+}
+
+// ------------------------------------------------------------ allocation-free scratch
+// Device memory of dehaze_residual_noalloc: the summed pair (sum r^2, sum Phi^2)
+// in the first 256 bytes, then one pair per residual block.  Each GPU holds its
+// own copy for the life of the process.  In host code `scratch` is a host-side
+// stand-in, not a device address: the address of the current device's copy is
+// looked up once per device (in dehaze_ctx_create) and only that is used.
+constexpr size_t kNoallocHead = 256;
+constexpr size_t kNoallocBytes = kNoallocHead + 2 * sizeof(double) * DEHAZE_NOALLOC_MAX_BLOCKS;
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// Looks up this device's copy of `scratch`; the device must be current.
+static int scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) {
+    set_error("device %d outside 0..%d", device, kMaxDevices - 1);
+    return DEHAZE_EINVAL;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return DEHAZE_OK;
+  void* ptr = nullptr;
+  DZ_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+  if (!ptr) {
+    set_error("no device address for the allocation-free scratch on device %d", device);
+    return DEHAZE_EHIP;
+  }
+  g_scratch_ptr[device] = ptr;
+  return DEHAZE_OK;
+}
+
+static void* scratch_ptr(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_ptr[device];
 }
 
 // ------------------------------------------------------------ workspace plans
@@ -160,6 +201,8 @@ int dehaze_ctx_create(dehaze_ctx** out, int device) {
   DZ_HIP(hipSetDevice(device));
   hipDeviceProp_t prop;
   DZ_HIP(hipGetDeviceProperties(&prop, device));
+  int rc = scratch_setup(device);
+  if (rc) return rc;
   dehaze_ctx* ctx = new (std::nothrow) dehaze_ctx();
   if (!ctx) { set_error("out of host memory"); return DEHAZE_EINVAL; }
   ctx->c.device = device;
@@ -388,6 +431,34 @@ int dehaze_residual(dehaze_ctx* ctx, const float* u, const float* phi, const flo
   *rho = h[1] > 0.0 ? std::sqrt(h[0]) / std::sqrt(h[1]) : std::sqrt(h[0]);
   if (!std::isfinite(*rho)) { set_error("residual is not finite"); return DEHAZE_ENONFINITE; }
   return DEHAZE_OK;
+}
+
+int dehaze_residual_noalloc(dehaze_ctx* ctx, const float* u, const float* phi, const float* lam, int H, int W,
+                            const dehaze_params* p, float* r, double* rho, void* stream) {
+  clear_error();
+  if (!ctx) { set_error("ctx is NULL"); return DEHAZE_EINVAL; }
+  if (!u || !phi || !lam || !rho) { set_error("u, phi, lam and rho are required"); return DEHAZE_EINVAL; }
+  if (H < 1 || W < 1) { set_error("image must be at least 1 x 1"); return DEHAZE_EINVAL; }
+  int rc = check_params(p);
+  if (rc) return rc;
+  const long long nb = (static_cast<long long>(W) + 63) / 64 * ((static_cast<long long>(H) + 15) / 16);
+  if (nb > DEHAZE_NOALLOC_MAX_BLOCKS) {
+    set_error("%d x %d needs %lld residual blocks; the allocation-free scratch holds %d (ceil(W/64) * ceil(H/16))",
+              H, W, nb, DEHAZE_NOALLOC_MAX_BLOCKS);
+    return DEHAZE_EINVAL;
+  }
+  char* base = static_cast<char*>(scratch_ptr(ctx->c.device));
+  if (!base) { set_error("allocation-free scratch not set up on device %d", ctx->c.device); return DEHAZE_EINVAL; }
+  DZ_HIP(hipSetDevice(ctx->c.device));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  double* sums = reinterpret_cast<double*>(base);
+  double* part = reinterpret_cast<double*>(base + kNoallocHead);
+  // every block writes its pair and the reduction overwrites `sums`, so the
+  // array needs no clearing between calls
+  const OpConst oc = make_opconst(*p);
+  if ((rc = launch_sweep(kResidual, u, r, phi, lam, H, W, W, oc, part, s))) return rc;
+  if ((rc = launch_reduce_pairs(part, static_cast<int>(nb), sums, s))) return rc;
+  return launch_rho_from_sums(sums, rho, s);
 }
 
 }  // extern "C"

@@ -159,5 +159,7 @@ int launch_sweep_strip(int mode, int K, int S, int C, const float* uin, float* u
                        const float* lam, int H, int W, int P, const OpConst& c, hipStream_t s);
 // Deterministic sum of `n` (a, b) double pairs into out[0..1].
 int launch_reduce_pairs(const double* partials, int n, double* out, hipStream_t s);
+// rho[0] = sqrt(sums[0]) / sqrt(sums[1]) (sqrt(sums[0]) when sums[1] is 0), on the device.
+int launch_rho_from_sums(const double* sums, double* rho, hipStream_t s);
 
 }  // namespace dz

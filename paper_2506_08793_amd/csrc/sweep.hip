@@ -204,6 +204,16 @@ __global__ __launch_bounds__(256) void k_reduce_pairs(const double* __restrict__
   }
 }
 
+// rho = ||r|| / ||Phi|| from the two sums (sum r^2, sum Phi^2); the norm of r
+// alone when Phi vanishes.  Correctly rounded float64 square roots and
+// division, as on the host.
+__global__ void k_rho_from_sums(const double* __restrict__ sums, double* __restrict__ rho) {
+  if (threadIdx.x == 0) {
+    const double a = sums[0], b = sums[1];
+    rho[0] = b > 0.0 ? sqrt(a) / sqrt(b) : sqrt(a);
+  }
+}
+
 template <int R>
 int launch_sweep_r(int mode, const float* uin, float* uout, const float* phi, const float* lam, int H,
                    int W, int P, const OpConst& c, double* partials, hipStream_t s) {
@@ -616,6 +626,12 @@ int launch_sweep(int mode, const float* uin, float* uout, const float* phi, cons
 
 int launch_reduce_pairs(const double* partials, int n, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_reduce_pairs, dim3(1), dim3(256), 0, s, partials, n, out);
+  DZ_CHECK_LAUNCH();
+  return DEHAZE_OK;
+}
+
+int launch_rho_from_sums(const double* sums, double* rho, hipStream_t s) {
+  hipLaunchKernelGGL(k_rho_from_sums, dim3(1), dim3(64), 0, s, sums, rho);
   DZ_CHECK_LAUNCH();
   return DEHAZE_OK;
 }
