@@ -60,6 +60,9 @@ extern "C" {
 #define DEHAZE_HWC 0          /* interleaved RGB */
 #define DEHAZE_CHW 1          /* planar RGB */
 
+#define DEHAZE_U_F32 0         /* u is returned as float32 (u points to 3 planes of float) */
+#define DEHAZE_U_F64 1         /* u is returned as float64 (u points to 3 planes of double) */
+
 #define DEHAZE_PAPER_EXPLICIT 0  /* u += tau r(u), Appendix A-1 as printed */
 #define DEHAZE_JACOBI         1  /* u += theta r(u) / diag(L_D(u)), D recomputed every sweep */
 #define DEHAZE_PICARD_KRYLOV  2  /* lagged diffusivity: u_{n+1} = L_{D(u_n)}^-1 Phi, each
@@ -112,7 +115,18 @@ typedef struct dehaze_params {
   int32_t dark_scales;      /* t_d averaged over patch sides ((patch - 1) >> k) | 1, k < dark_scales: a
                                reading of the multiscale dark channel Table II ablates; 1 (default) = off */
   double  guided_eps;       /* guided-filter regulariser (default 1e-3) */
-  int32_t reserved[4];      /* must be zero */
+  int32_t u_state;          /* precision of the returned u: DEHAZE_U_F32 (default) rounds the solution to
+                               float32; DEHAZE_U_F64 returns it in float64, and then the `u` argument of
+                               dehaze_solve and the `u` of every dehaze_image must point to 3 * H * W
+                               doubles (cast to float*).  The lagged-diffusivity solve iterates in float64,
+                               so only DEHAZE_U_F64 hands back an iterate whose residual meets rel_tol
+                               (rel_residual_out == rel_residual); the sweep schemes iterate in float32
+                               and return that iterate widened */
+  int32_t krylov_rows;      /* rows per wavefront of the BiCGSTAB strip kernels (lagged-diffusivity
+                               solves, R = 2): a multiple of 16 up to 512; 0 = time the candidates on the
+                               first solve of each batch composition (synchronises) and keep the fastest
+                               in the context.  Every value gives bit-identical results */
+  int32_t reserved[2];      /* must be zero */
 } dehaze_params;
 
 typedef struct dehaze_stats {
@@ -128,11 +142,12 @@ typedef struct dehaze_stats {
   int32_t status;           /* DEHAZE_OK, DEHAZE_ENOTCONV or DEHAZE_ENONFINITE for this image */
   int32_t restarts;         /* 1 if the solve stalled from its given start and restarted from Phi */
   int32_t stalled;          /* 1 if the solve stopped early because rho stopped falling */
-  double  rel_residual_out; /* the same residual at the returned float32 u.  Rounding u to float32
-                               perturbs each flux by up to ulp(u) / eps, so where u is large and flat
-                               this sits at a floor well above rel_residual (e.g. 7.6e-4 for a 1080p
-                               image with u near 32 whose iterate met 1e-5); the sweep schemes iterate
-                               in float32 and report rel_residual here too */
+  double  rel_residual_out; /* the same residual at the returned u.  With DEHAZE_U_F32, rounding u to
+                               float32 perturbs each flux by up to ulp(u) / eps, so where u is large
+                               and flat this sits at a floor well above rel_residual (e.g. 7.6e-4 for
+                               a 1080p image with u near 32 whose iterate met 1e-5); with DEHAZE_U_F64
+                               it equals rel_residual.  The sweep schemes iterate in float32 and report
+                               rel_residual here too */
 } dehaze_stats;
 
 typedef struct dehaze_ctx dehaze_ctx;
@@ -174,8 +189,9 @@ const char* dehaze_strerror(int code);
  * Errors: EINVAL (H or W < 1, pitch < W, even or non-positive patch,
  * t0, eps or sigma <= 0, omega outside (0, 1], unknown dtype or layout, NULL
  * I or A_out), ENOMEM (ws_bytes too small), EHIP.  A_in lives on the device
- * and is not read back: a non-positive A_in gives non-finite t_d, t, lam and
- * phi, which a later dehaze_solve reports as DEHAZE_ENONFINITE. */
+ * and is not read back: an A_in (or, in dehaze_solve and dehaze_batch, an A)
+ * with a channel that is not positive and finite makes t_d, t, lam and phi
+ * NaN, which dehaze_solve and dehaze_batch report as DEHAZE_ENONFINITE. */
 size_t dehaze_prior_workspace_size(int H, int W, const dehaze_params* p);
 int dehaze_prior(dehaze_ctx* ctx, const void* I, int dtype, int layout, int H, int W, int pitch,
                  const dehaze_params* p, const float* A_in,
@@ -233,6 +249,17 @@ typedef struct dehaze_image {
 } dehaze_image;
 
 size_t dehaze_batch_workspace_size(int n, const dehaze_image* imgs, const dehaze_params* p);
+/* Rows per wavefront of the BiCGSTAB strip kernels that a lagged-diffusivity
+ * solve of this batch (or, with n = 1, dehaze_solve of that image) uses for
+ * each image: rows[i] (host, n entries) is the height the context timed as
+ * fastest for this composition of image sizes (*tuned = 1), else
+ * p->krylov_rows or the size rule the timing starts from (*tuned = 0).
+ * rows[i] = 0 for every image when the tile kernels run instead: g_radius !=
+ * 2, or some image's planes exceed the strips' 32-bit byte offsets ((H + 1) *
+ * roundup(W + 1, 64) * 4 >= 2^31).  Only the sizes of imgs are read; ctx may
+ * be NULL (the rule alone).  Host only, no device work.  Errors: EINVAL. */
+int dehaze_batch_strip_rows(const dehaze_ctx* ctx, int n, const dehaze_image* imgs, const dehaze_params* p,
+                            int* rows, int* tuned);
 int dehaze_batch(dehaze_ctx* ctx, int n, const dehaze_image* imgs, int dtype, int layout,
                  const dehaze_params* p, void* ws, size_t ws_bytes, dehaze_stats* stats, void* stream);
 

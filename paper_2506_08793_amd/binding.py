@@ -20,6 +20,7 @@ OK, EINVAL, ENOMEM, EHIP, ENOTCONV, ENONFINITE = 0, -1, -2, -3, -4, -5
 U8, F32 = 0, 1
 HWC, CHW = 0, 1
 PAPER_EXPLICIT, JACOBI, PICARD_KRYLOV = 0, 1, 2
+U_F32, U_F64 = 0, 1
 SCHEMES = {"explicit": PAPER_EXPLICIT, "jacobi": JACOBI, "picard": PICARD_KRYLOV}
 
 
@@ -34,7 +35,7 @@ class Params(ctypes.Structure):
         ("adaptive", c_int32), ("edge_preserving", c_int32), ("sweeps_per_launch", c_int32),
         ("inner_refine", c_int32), ("strip_rows", c_int32), ("lane_columns", c_int32),
         ("stall_window", c_int32), ("guided_radius", c_int32), ("dark_scales", c_int32),
-        ("guided_eps", c_double), ("reserved", c_int32 * 4),
+        ("guided_eps", c_double), ("u_state", c_int32), ("krylov_rows", c_int32), ("reserved", c_int32 * 2),
     ]
 
     def replace(self, **kw) -> "Params":
@@ -99,6 +100,7 @@ _SIGS = {
                              c_void_p, c_void_p, c_void_p, c_size_t, _S, c_void_p]),
     "dehaze_batch_workspace_size": (c_size_t, [c_int, POINTER(Image), _P]),
     "dehaze_batch": (c_int, [c_void_p, c_int, POINTER(Image), c_int, c_int, _P, c_void_p, c_size_t, _S, c_void_p]),
+    "dehaze_batch_strip_rows": (c_int, [c_void_p, c_int, POINTER(Image), _P, POINTER(c_int), POINTER(c_int)]),
     "dehaze_cnn_param_count": (c_size_t, []),
     "dehaze_cnn_set_weights": (c_int, [c_void_p, c_void_p, c_size_t]),
     "dehaze_cnn_get_weights": (c_int, [c_void_p, c_void_p, c_size_t]),
@@ -226,8 +228,11 @@ def dehaze_solve(ctx: Context, I: torch.Tensor, t: torch.Tensor, A: torch.Tensor
         if tens is not None and (tuple(tens.shape) != shape or not tens.is_contiguous()
                                  or tens.dtype != torch.float32 or not tens.is_cuda):
             raise ValueError(f"{name} must be a contiguous float32 device tensor of shape {shape}")
+    u_dtype = torch.float64 if p.u_state == U_F64 else torch.float32
     if u is None:
-        u = torch.empty((3, H, W), dtype=torch.float32, device=dev)
+        u = torch.empty((3, H, W), dtype=u_dtype, device=dev)
+    elif u.dtype != u_dtype or tuple(u.shape) != (3, H, W) or not u.is_contiguous():
+        raise ValueError(f"u must be a contiguous {u_dtype} tensor of shape {(3, H, W)}")
     need = _lib.dehaze_solve_workspace_size(H, W, ctypes.byref(p))
     if ws is None or ws.numel() < need:
         ws = _workspace(need, dev)
@@ -276,10 +281,13 @@ def dehaze_residual_noalloc(ctx: Context, u: torch.Tensor, phi: torch.Tensor, la
 
 
 def dehaze_batch(ctx: Context, images, params: Params = None, layout: str = "CHW", t=None, A=None, u0=None,
-                 want_t: bool = False, stats: bool = True, ws: torch.Tensor = None, outs=None):
+                 want_t: bool = False, stats: bool = True, ws: torch.Tensor = None, outs=None,
+                 allow_nonfinite: bool = False):
     """Solve a list of device images (each CHW (3,H,W) or HWC (H,W,3), one dtype).
 
     t, A, u0: optional per-image lists (None entries are estimated / Phi).
+    allow_nonfinite: return normally when an image met a non-finite value (its
+    stats entry says which) instead of raising.
     Returns (list of u, list of stats dicts or None, list of t or None, list of A).
     """
     p = params or dehaze_params_default()
@@ -294,7 +302,10 @@ def dehaze_batch(ctx: Context, images, params: Params = None, layout: str = "CHW
             dtype0, lay0 = dtype, lay
         elif dtype != dtype0:
             raise ValueError("all images of a batch share one dtype")
-        u = outs[i] if outs is not None else torch.empty((3, H, W), dtype=torch.float32, device=I.device)
+        u_dtype = torch.float64 if p.u_state == U_F64 else torch.float32
+        u = outs[i] if outs is not None else torch.empty((3, H, W), dtype=u_dtype, device=I.device)
+        if u.dtype != u_dtype or tuple(u.shape) != (3, H, W) or not u.is_contiguous():
+            raise ValueError(f"output {i} must be a contiguous {u_dtype} tensor of shape {(3, H, W)}")
         ti = None if t is None else t[i]
         Ai = None if A is None else A[i]
         ui = None if u0 is None else u0[i]
@@ -314,7 +325,7 @@ def dehaze_batch(ctx: Context, images, params: Params = None, layout: str = "CHW
     st = (Stats * n)() if stats else None
     rc = _lib.dehaze_batch(ctx.handle, n, arr, dtype0, lay0, ctypes.byref(p), ws.data_ptr(), ws.numel(),
                            st if st is not None else None, _stream())
-    _check(rc, allow=(OK, ENOTCONV))
+    _check(rc, allow=(OK, ENOTCONV, ENONFINITE) if allow_nonfinite else (OK, ENOTCONV))
     return us, ([x.as_dict() for x in st] if st is not None else None), ts, As
 
 
@@ -325,6 +336,21 @@ def batch_workspace_bytes(shapes, params: Params = None) -> int:
     for i, (H, W) in enumerate(shapes):
         arr[i] = Image(1, H, W, W, 0, 1, None, None, None, None, None)
     return int(_lib.dehaze_batch_workspace_size(n, arr, ctypes.byref(p)))
+
+
+def dehaze_batch_strip_rows(ctx, shapes, params: Params = None):
+    """(rows per image, tuned) of the BiCGSTAB strip kernels for a batch of
+    (H, W) shapes; ctx may be None (the size rule alone)."""
+    p = params or dehaze_params_default()
+    n = len(shapes)
+    arr = (Image * n)()
+    for i, (H, W) in enumerate(shapes):
+        arr[i] = Image(1, H, W, W, 0, 1, None, None, None, None, None)
+    rows = (c_int * n)()
+    tuned = c_int()
+    _check(_lib.dehaze_batch_strip_rows(None if ctx is None else ctx.handle, n, arr, ctypes.byref(p), rows,
+                                        ctypes.byref(tuned)))
+    return list(rows), bool(tuned.value)
 
 
 # ---------------------------------------------------------------- network

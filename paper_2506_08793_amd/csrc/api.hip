@@ -65,6 +65,14 @@ int check_params(const dehaze_params* p) {
     return DEHAZE_EINVAL;
   }
   if (p->dark_scales < 1 || p->dark_scales > 4) { set_error("dark_scales must lie in 1..4"); return DEHAZE_EINVAL; }
+  if (p->krylov_rows < 0 || p->krylov_rows > 512 || p->krylov_rows % 16 != 0) {
+    set_error("krylov_rows must be 0 or a multiple of 16 up to 512");
+    return DEHAZE_EINVAL;
+  }
+  if (p->u_state != DEHAZE_U_F32 && p->u_state != DEHAZE_U_F64) {
+    set_error("u_state must be DEHAZE_U_F32 or DEHAZE_U_F64");
+    return DEHAZE_EINVAL;
+  }
   for (int r : p->reserved)
     if (r != 0) { set_error("reserved fields of dehaze_params must be zero"); return DEHAZE_EINVAL; }
   if (!(p->inner_rtol > 0.0)) { set_error("inner_rtol must be positive"); return DEHAZE_EINVAL; }
@@ -316,6 +324,16 @@ int dehaze_batch(dehaze_ctx* ctx, int n, const dehaze_image* imgs, int dtype, in
   }
   DZ_HIP(hipSetDevice(ctx->c.device));
   return solve_batch(ctx->c, n, imgs, dtype, layout, *p, ws, stats, static_cast<hipStream_t>(stream));
+}
+
+int dehaze_batch_strip_rows(const dehaze_ctx* ctx, int n, const dehaze_image* imgs, const dehaze_params* p,
+                            int* rows, int* tuned) {
+  clear_error();
+  int rc = check_params(p);
+  if (rc) return rc;
+  if ((rc = check_batch(n, imgs))) return rc;
+  if (!rows || !tuned) { set_error("rows and tuned are required"); return DEHAZE_EINVAL; }
+  return batch_strip_rows(ctx ? &ctx->c : nullptr, n, imgs, *p, rows, tuned);
 }
 
 size_t dehaze_cnn_param_count(void) { return cnn_param_count(); }

@@ -58,6 +58,7 @@ struct Carver {
 struct GraphCache;  // captured outer-step graphs (solver.hip)
 struct CnnState;    // warm-start network weights and optimiser state (cnn.hip)
 struct SweepTune;   // autotuned sweep launch shapes per image size (solver.hip)
+struct KrylovTune;  // autotuned BiCGSTAB strip heights per batch composition (solver.hip)
 struct Ctx {
   int device = 0;
   int num_cus = 256;
@@ -65,6 +66,7 @@ struct Ctx {
   GraphCache* graphs = nullptr;
   CnnState* cnn = nullptr;
   SweepTune* tune = nullptr;
+  KrylovTune* ktune = nullptr;
 };
 
 // ---------------------------------------------------------------- launchers
@@ -120,8 +122,9 @@ int launch_prior_fused(const float* m, const float* Ip, int P, const float* t_in
 int launch_warm_base(float* u0, const float* phi, const float* lam, int P, int H, int W, bool nonlocal, bool add,
                      hipStream_t s);
 
-// Strided 3-plane copy (pitches in elements).
+// Strided 3-plane copy (pitches in elements), and the same widened to float64.
 int launch_copy3(const float* src, int sp, float* dst, int dp, int H, int W, hipStream_t s);
+int launch_copy3_wide(const float* src, int sp, double* dst, int dp, int H, int W, hipStream_t s);
 
 // Sweep constants derived from the parameters.
 struct OpConst {

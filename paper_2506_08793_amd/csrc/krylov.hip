@@ -43,6 +43,10 @@ KConst make_kconst(const dehaze_params& p) {
 
 int krylov_tiles(int H, int W) { return ((W + kKTX - 1) / kKTX) * ((H + kKTY - 1) / kKTY); }
 int krylov_units(int H, int W, int us) { return 3 * ((W + kUOW - 1) / kUOW) * ((H + us - 1) / us); }
+int krylov_blocks(int H, int W) { return krylov_units(H, W, kSBlk); }
+bool krylov_strips_fit(int H, int W) {
+  return static_cast<long long>(H + 1) * padded_pitch(W + 1) * 4 < (1LL << 31);
+}
 
 // Taller strips cost less per row (fewer halo rows and partial sums) but give
 // fewer wavefronts.  In a small launch each image takes the tallest of 128,
@@ -77,7 +81,7 @@ struct KCarve {
   size_t bytes;
 };
 
-KCarve carve(void* base, int H, int W, int tile0, int unit0, int us) {
+KCarve carve(void* base, int H, int W, int tile0, int unit0, int blk0, int us) {
   KCarve k{};
   const int P = padded_pitch(W + 1);
   const size_t plane = static_cast<size_t>(H) * P;
@@ -94,6 +98,8 @@ KCarve carve(void* base, int H, int W, int tile0, int unit0, int us) {
   m.us = us;
   m.nunits = krylov_units(H, W, us);
   m.unit0 = unit0;
+  m.nblk = krylov_blocks(H, W);
+  m.blk0 = blk0;
   m.phi = cv.take<float>(3 * plane);
   m.lam = cv.take<float>(plane);
   m.u = cv.take<double>(3 * plane);
@@ -171,7 +177,7 @@ __device__ __forceinline__ void write_partials(double (&v)[N], double* part, int
 template <int N, bool UNITS = false>
 __device__ __forceinline__ void image_sums(const KImg& I, const double* part, double (&tot)[N]) {
   for (int k = 0; k < N; ++k) tot[k] = 0.0;
-  const int n = UNITS ? I.nunits : I.ntiles, first = UNITS ? I.unit0 : I.tile0;
+  const int n = UNITS ? I.nblk : I.ntiles, first = UNITS ? I.blk0 : I.tile0;
   for (int q = threadIdx.x; q < n; q += NT)
     for (int k = 0; k < N; ++k) tot[k] += part[static_cast<size_t>(first + q) * kKPart + k];
   block_sum<N>(tot);
@@ -215,6 +221,15 @@ __global__ __launch_bounds__(NT) void k_out_u(KImg I, float* __restrict__ out) {
   for (int c = 0; c < 3; ++c)
     out[(static_cast<size_t>(c) * I.H + y) * I.W + x] =
         static_cast<float>(I.u[c * plane + static_cast<size_t>(y) * I.P + x]);
+}
+
+__global__ __launch_bounds__(NT) void k_out_u64(KImg I, double* __restrict__ out) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x >= I.W) return;
+  const size_t plane = static_cast<size_t>(I.H) * I.P;
+  for (int c = 0; c < 3; ++c)
+    out[(static_cast<size_t>(c) * I.H + y) * I.W + x] = I.u[c * plane + static_cast<size_t>(y) * I.P + x];
 }
 
 // ------------------------------------------------------------ residual pass
@@ -645,7 +660,7 @@ __global__ __launch_bounds__(256) void k_bicg_strip(const KImg* __restrict__ img
                                                      const int* __restrict__ unit_img, double* upart, KConst kc,
                                                      int nunits) {
 #pragma clang fp contract(off)
-  constexpr int NA = MODE == 0 ? 2 : 1;  // partial sums
+  constexpr int NACC = MODE == 0 ? 1 : 3;  // dot products: (rhat, v); (t, s), (t, t), (s, s)
   constexpr int RING = 4, AHEAD = 3;
   const int gw = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (gw >= nunits) return;
@@ -654,9 +669,10 @@ __global__ __launch_bounds__(256) void k_bicg_strip(const KImg* __restrict__ img
   const KImg I = imgs[im];
   const KScal* sc = scal + im;
   // uniform per wavefront; the first iteration of an inner solve has its own
-  // instantiation
-  if (sc->converged || sc->inner_done || (sc->it == 1) != FIRST) return;
-  const int par = sc->it & 1;
+  // instantiation (launch-shape trials run regardless, on whatever the
+  // buffers hold, and their outputs are overwritten before use)
+  if (!kc.trial && (sc->converged || sc->inner_done || (sc->it == 1) != FIRST)) return;
+  const int par = kc.trial ? 1 : (sc->it & 1);
   const int u = gw - I.unit0;
   // column group fastest: the four wavefronts of a workgroup (one XCD, one
   // L2) take adjacent column groups and share the cache lines between them
@@ -685,9 +701,9 @@ __global__ __launch_bounds__(256) void k_bicg_strip(const KImg* __restrict__ img
   const __amdgpu_buffer_rsrc_t b_lo = plane_rsrc(MODE == 0 ? pick(I.v, par) + c * plane : I.t + c * plane, pb);
   const int vx = min(max(x, 0), I.W - 1) * 4;   // cell columns
   const int vf = min(max(x, 0), I.W) * 4;       // x-face columns (W + 1 faces)
-  const float beta = FIRST ? 0.0f : static_cast<float>(sc->beta);
-  const float omega = static_cast<float>(sc->omega);
-  const float alpha = static_cast<float>(sc->alpha);
+  const float beta = FIRST || kc.trial ? 0.0f : static_cast<float>(sc->beta);
+  const float omega = kc.trial ? 0.0f : static_cast<float>(sc->omega);
+  const float alpha = kc.trial ? 0.0f : static_cast<float>(sc->alpha);
   const bool nl = kc.nonlocal_term != 0;
   const float w0 = nl ? kc.w[2] : 0.0f, w1 = nl ? kc.w[1] : 0.0f, w2 = nl ? kc.w[0] : 0.0f;
 
@@ -762,19 +778,32 @@ __global__ __launch_bounds__(256) void k_bicg_strip(const KImg* __restrict__ img
     GH[3] = ghn;
     Q[3] = qv;
   };
-  // head: rows y0 - 2 .. y0 + 1 fill the windows; then rows j = y0 .. y1 - 1
+  // the sums of each block of kSBlk output rows go to that block's own slot
+  // (column group fastest, then channel, then block), whatever the strip
+  // height, so the per-image totals are summed in one fixed order
+  auto flush = [&](int blk) {
+    const size_t slot = static_cast<size_t>(I.blk0 + (blk * 3 + c) * I.ucols + col) * kKPart;
+    for (int k = 0; k < NACC; ++k) {
+      const double v = wave_sum(acc[k]);
+      if (lane == 0) upart[slot + k] = v;
+      acc[k] = 0.0;
+    }
+  };
+  // head: rows y0 - 2 .. y0 + 1 fill the windows; then rows j = y0 .. y1 - 1,
+  // four per loop trip, a block complete after every fourth trip (y0 is a
+  // multiple of kSBlk = 16)
+  static_assert(kSBlk == 4 * RING, "one partial-sum block per four loop trips");
   int r = rs0;
 #pragma unroll
   for (int q = 0; q < RING; ++q) step(r + q, q, false);
   r += RING;
+  int trips = 0;
   for (; r - 2 < y1; r += RING) {
 #pragma unroll
     for (int q = 0; q < RING; ++q) step(r + q, q, true);
+    if ((++trips & 3) == 0) flush(y0 / kSBlk + (trips >> 2) - 1);
   }
-  for (int k = 0; k < (MODE == 0 ? 1 : 3); ++k) acc[k] = wave_sum(acc[k]);
-  if (lane == 0)
-    for (int k = 0; k < (MODE == 0 ? 1 : 3); ++k) upart[static_cast<size_t>(gw) * kKPart + k] = acc[k];
-  (void)NA;
+  if (trips & 3) flush(y0 / kSBlk + (trips >> 2));
 }
 
 // (c) x += alpha M^-1 p + omega M^-1 s; r = s - omega t; rho = (rhat, r); beta.
@@ -901,27 +930,36 @@ __global__ __launch_bounds__(NT) void k_update(const KImg* __restrict__ imgs, co
 
 }  // namespace
 
-size_t krylov_image_bytes(int H, int W) { return carve(nullptr, H, W, 0, 0, 32).bytes; }
+size_t krylov_image_bytes(int H, int W) { return carve(nullptr, H, W, 0, 0, 0, 32).bytes; }
 
-KImg krylov_carve(void* base, int H, int W, int tile0, int unit0, int us) {
-  return carve(base, H, W, tile0, unit0, us).img;
+KImg krylov_carve(void* base, int H, int W, int tile0, int unit0, int blk0, int us) {
+  return carve(base, H, W, tile0, unit0, blk0, us).img;
+}
+
+int krylov_upload_strips(const KrylovBatch& b, const KImg* h_imgs, hipStream_t s) {
+  for (int i = 0; i < b.nimg; ++i) {
+    const KImg& m = h_imgs[i];
+    hipLaunchKernelGGL(k_set_desc, dim3(1), dim3(1), 0, s, const_cast<KImg*>(b.d_imgs), i, m);
+    DZ_CHECK_LAUNCH();
+    if (b.d_unit_img && b.nunits > 0) {
+      hipLaunchKernelGGL(k_tile_map, dim3((m.nunits + NT - 1) / NT), dim3(NT), 0, s,
+                         const_cast<int*>(b.d_unit_img), m.unit0, m.nunits, i);
+      DZ_CHECK_LAUNCH();
+    }
+  }
+  return DEHAZE_OK;
 }
 
 int krylov_init(const KrylovBatch& b, const KImg* h_imgs, const float* const* u0, hipStream_t s) {
   hipLaunchKernelGGL(k_scal_reset, dim3((b.nimg + NT - 1) / NT), dim3(NT), 0, s, b.d_scal, b.nimg);
   DZ_CHECK_LAUNCH();
+  int rc = krylov_upload_strips(b, h_imgs, s);
+  if (rc) return rc;
   for (int i = 0; i < b.nimg; ++i) {
     const KImg& m = h_imgs[i];
-    hipLaunchKernelGGL(k_set_desc, dim3(1), dim3(1), 0, s, const_cast<KImg*>(b.d_imgs), i, m);
-    DZ_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_tile_map, dim3((m.ntiles + NT - 1) / NT), dim3(NT), 0, s,
                        const_cast<int*>(b.d_tile_img), m.tile0, m.ntiles, i);
     DZ_CHECK_LAUNCH();
-    if (b.d_unit_img) {
-      hipLaunchKernelGGL(k_tile_map, dim3((m.nunits + NT - 1) / NT), dim3(NT), 0, s,
-                         const_cast<int*>(b.d_unit_img), m.unit0, m.nunits, i);
-      DZ_CHECK_LAUNCH();
-    }
     hipLaunchKernelGGL(k_init_u, dim3((m.W + NT - 1) / NT, m.H), dim3(NT), 0, s, m, u0 ? u0[i] : nullptr,
                        b.d_scal + i);
     DZ_CHECK_LAUNCH();
@@ -954,6 +992,35 @@ int krylov_linear_residual(const KrylovBatch& b, const KConst& c, hipStream_t s)
 int krylov_snapshot(const KrylovBatch& b, hipStream_t s) {
   hipLaunchKernelGGL(k_snapshot, dim3(b.ntiles), dim3(NT), 0, s, b.d_imgs, b.d_scal, b.d_tile_img);
   DZ_CHECK_LAUNCH();
+  return DEHAZE_OK;
+}
+
+int krylov_time_strips(const KrylovBatch& b, const KConst& c, int reps, hipStream_t s, float* us) {
+  KConst t = c;
+  t.trial = 1;
+  const dim3 ug((b.nunits + 3) / 4);
+  hipEvent_t e0, e1;
+  DZ_HIP(hipEventCreate(&e0));
+  DZ_HIP(hipEventCreate(&e1));
+  int rc = DEHAZE_OK;
+  // one untimed launch first: caches, clocks
+  for (int i = 0; i <= reps && rc == DEHAZE_OK; ++i) {
+    if (i == 1 && hipEventRecord(e0, s) != hipSuccess) rc = DEHAZE_EHIP;
+    hipLaunchKernelGGL((k_bicg_strip<0, false>), ug, dim3(256), 0, s, b.d_imgs, b.d_scal, b.d_unit_img, b.d_upart, t,
+                       b.nunits);
+    if (hipGetLastError() != hipSuccess) rc = DEHAZE_EHIP;
+  }
+  float ms = 0.0f;
+  if (rc == DEHAZE_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                          hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+    rc = DEHAZE_EHIP;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) {
+    set_error("timing the BiCGSTAB strip kernel failed");
+    return rc;
+  }
+  *us = 1000.0f * ms / static_cast<float>(reps);
   return DEHAZE_OK;
 }
 
@@ -1010,6 +1077,12 @@ int krylov_update(const KrylovBatch& b, hipStream_t s) {
 
 int krylov_output(const KImg& img, float* out, hipStream_t s) {
   hipLaunchKernelGGL(k_out_u, dim3((img.W + NT - 1) / NT, img.H), dim3(NT), 0, s, img, out);
+  DZ_CHECK_LAUNCH();
+  return DEHAZE_OK;
+}
+
+int krylov_output64(const KImg& img, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_out_u64, dim3((img.W + NT - 1) / NT, img.H), dim3(NT), 0, s, img, out);
   DZ_CHECK_LAUNCH();
   return DEHAZE_OK;
 }

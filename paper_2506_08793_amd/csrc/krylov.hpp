@@ -33,12 +33,17 @@ constexpr int kKPart = 4;  // doubles of partial sums per tile
 // Strip wavefronts of the BiCGSTAB operator kernels (Gaussian radius 2): one
 // wavefront per (channel, group of kUOW columns, strip of KImg::us rows).
 constexpr int kUOW = 60;
+// Their dot products are summed per block of kSBlk rows (strip heights are
+// multiples of it), so the sums, and every rounding that follows from them,
+// do not depend on the strip height.
+constexpr int kSBlk = 16;
 
 struct KImg {
   int H, W, P;             // P: pitch of every plane, >= W + 1
   int tiles_x, ntiles, tile0;
   int ucols, nunits, unit0; // strip wavefronts: column groups, count, first global index
-  int us;                   // rows per strip wavefront
+  int us;                   // rows per strip wavefront (a multiple of kSBlk)
+  int nblk, blk0;           // partial-sum blocks (channel, column group, kSBlk rows): count, first index
   const float* phi;        // 3 planes
   const float* lam;        // 1 plane
   double* u;               // 3 planes, the iterate
@@ -97,6 +102,7 @@ struct KConst {
   int stall_window;        // 0: never restart
   int max_inner;
   int max_outer;
+  int trial;               // launch-shape trials: the strip kernels skip the per-image state tests
 };
 KConst make_kconst(const dehaze_params& p);
 
@@ -104,12 +110,17 @@ KConst make_kconst(const dehaze_params& p);
 size_t krylov_image_bytes(int H, int W);
 int krylov_tiles(int H, int W);
 int krylov_units(int H, int W, int us);
-// Rows per strip wavefront of each image of a launch of n images (us[i]).
+int krylov_blocks(int H, int W);
+// Whether the strip kernels can address an image (32-bit byte offsets within
+// every plane, the y-face plane of H + 1 rows included).
+bool krylov_strips_fit(int H, int W);
+// Rows per strip wavefront of each image of a launch of n images (us[i]) by
+// the size rule, the tuner's starting point and fallback.
 void krylov_strip_rows(int n, const int* H, const int* W, int* us);
 // Fills a descriptor whose planes live at `base` (krylov_image_bytes bytes,
 // 256-byte aligned); phi/lam are carved here too and returned through the
 // descriptor (the front end writes them).
-KImg krylov_carve(void* base, int H, int W, int tile0, int unit0, int us);
+KImg krylov_carve(void* base, int H, int W, int tile0, int unit0, int blk0, int us);
 
 struct KrylovBatch {
   const KImg* d_imgs;      // device copy of the descriptors
@@ -123,7 +134,11 @@ struct KrylovBatch {
   int nunits;
 };
 
-// Starting iterate: u = u0 (float, dense pitch W) or Phi; resets the scalars.
+// Uploads the descriptors and the strip-wavefront -> image map (b.nunits
+// wavefronts in all; none when b.nunits is 0).
+int krylov_upload_strips(const KrylovBatch& b, const KImg* h_imgs, hipStream_t s);
+// Starting iterate: u = u0 (float, dense pitch W) or Phi; resets the scalars
+// and uploads the descriptors and maps.
 int krylov_init(const KrylovBatch& b, const KImg* h_imgs, const float* const* u0, hipStream_t s);
 // Residual pass (final != 0: evaluate every image, converged or not).
 int krylov_residual(const KrylovBatch& b, const KConst& c, int final, hipStream_t s);
@@ -132,13 +147,18 @@ int krylov_residual(const KrylovBatch& b, const KConst& c, int final, hipStream_
 int krylov_linear_residual(const KrylovBatch& b, const KConst& c, hipStream_t s);
 // u_n := u for every image still iterating.
 int krylov_snapshot(const KrylovBatch& b, hipStream_t s);
+// Times one launch of the strip operator kernel (a) over every image with the
+// descriptors currently on the device (trial mode: no state tests, results
+// discarded); *us receives the average in microseconds over `reps` launches.
+int krylov_time_strips(const KrylovBatch& b, const KConst& c, int reps, hipStream_t s, float* us);
 // One BiCGSTAB iteration of every image inside an inner solve (each image
 // keeps its own iteration count; an inner solve ends at its tolerance or after
 // max_inner iterations).
 int krylov_inner(const KrylovBatch& b, const KConst& c, hipStream_t s);
 // u += delta.
 int krylov_update(const KrylovBatch& b, hipStream_t s);
-// u (float64) -> out (float, dense pitch W).
+// u (float64) -> out (float, dense pitch W), or unchanged into a double array.
 int krylov_output(const KImg& img, float* out, hipStream_t s);
+int krylov_output64(const KImg& img, double* out, hipStream_t s);
 
 }  // namespace dz

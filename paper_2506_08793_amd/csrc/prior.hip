@@ -485,6 +485,20 @@ __global__ __launch_bounds__(256) void k_prior_fused(const float* __restrict__ m
   const size_t e = static_cast<size_t>(y) * P + x;
   const size_t plane = static_cast<size_t>(H) * P;
   const size_t oe = static_cast<size_t>(y) * o.op + x;
+  // the airlight of the scattering model is positive in every channel; a
+  // caller-supplied A that is not (A lives on the device and is never read
+  // back) turns every output into NaN, which the solve reports as non-finite
+  if (!(a0 > 0.0 && a1 > 0.0 && a2 > 0.0 && a0 < INFINITY && a1 < INFINITY && a2 < INFINITY)) {
+    const float nan = __builtin_nanf("");
+    if (o.t_d) o.t_d[static_cast<size_t>(y) * o.tp + x] = nan;
+    if (o.t && (m || tds || o.t != t_in)) o.t[static_cast<size_t>(y) * o.tp + x] = nan;
+    if (o.lam) o.lam[oe] = nan;
+    if (o.phi) {
+      const size_t oplane = static_cast<size_t>(H) * o.op;
+      o.phi[oe] = o.phi[oplane + oe] = o.phi[2 * oplane + oe] = nan;
+    }
+    return;
+  }
   float t32;
   if (tds) {
     // multiscale: the mean over the scales of the per-scale t_d, rounded once
@@ -671,6 +685,17 @@ __global__ __launch_bounds__(256) void k_copy3(const float* __restrict__ src, in
     dst[(static_cast<size_t>(c) * H + y) * dp + x] = src[(static_cast<size_t>(c) * H + y) * sp + x];
 }
 
+__global__ __launch_bounds__(256) void k_copy3_wide(const float* __restrict__ src, int sp, double* __restrict__ dst,
+                                                     int dp, int H, int W) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x >= W) return;
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+    dst[(static_cast<size_t>(c) * H + y) * dp + x] =
+        static_cast<double>(src[(static_cast<size_t>(c) * H + y) * sp + x]);
+}
+
 // Analytic part of the warm start: where the solution is smooth G(u) ~ u and
 // the diffusion term is small, so the main PDE reduces to lambda u = Phi and
 // B = Phi / lambda.  Without lambda G (or with lambda = 0) B = Phi.  With add,
@@ -848,6 +873,13 @@ int launch_warm_base(float* u0, const float* phi, const float* lam, int P, int H
 int launch_copy3(const float* src, int sp, float* dst, int dp, int H, int W, hipStream_t s) {
   dim3 grid((W + 255) / 256, H);
   hipLaunchKernelGGL(k_copy3, grid, dim3(256), 0, s, src, sp, dst, dp, H, W);
+  DZ_CHECK_LAUNCH();
+  return DEHAZE_OK;
+}
+
+int launch_copy3_wide(const float* src, int sp, double* dst, int dp, int H, int W, hipStream_t s) {
+  dim3 grid((W + 255) / 256, H);
+  hipLaunchKernelGGL(k_copy3_wide, grid, dim3(256), 0, s, src, sp, dst, dp, H, W);
   DZ_CHECK_LAUNCH();
   return DEHAZE_OK;
 }

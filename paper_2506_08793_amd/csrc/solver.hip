@@ -207,7 +207,9 @@ int run_sweeps(Ctx& ctx, const SolveArgs& a, const dehaze_params& p, dehaze_stat
       if (!std::isfinite(rho)) status = DEHAZE_ENONFINITE;
     }
   }
-  if ((rc = launch_copy3(cur, pl.P, a.u, W, H, W, s))) return rc;
+  if (p.u_state == DEHAZE_U_F64) rc = launch_copy3_wide(cur, pl.P, reinterpret_cast<double*>(a.u), W, H, W, s);
+  else rc = launch_copy3(cur, pl.P, a.u, W, H, W, s);
+  if (rc) return rc;
   if (st) {
     st->outer = done;
     st->converged = conv ? 1 : 0;
@@ -247,9 +249,11 @@ KrylovPlan plan_krylov(void* ws, int H, int W, bool warm) {
   char* arena = cv.take<char>(krylov_image_bytes(H, W));
   int us = 32;
   krylov_strip_rows(1, &H, &W, &us);
-  pl.img = krylov_carve(arena, H, W, 0, 0, us);
+  pl.img = krylov_carve(arena, H, W, 0, 0, 0, us);
   const int nt = krylov_tiles(H, W);
-  const int nu = pl.img.nunits;
+  // room for the most strip wavefronts (kSBlk rows each), one partial-sum
+  // slot per block
+  const int nu = pl.img.nblk;
   pl.Ip = cv.take<float>(3 * static_cast<size_t>(H) * pl.img.P);
   pl.d_imgs = cv.take<KImg>(1);
   pl.d_scal = cv.take<KScal>(1);
@@ -271,14 +275,15 @@ int read_scalars(const KrylovBatch& b, KScal* h, hipStream_t s) {
   return DEHAZE_OK;
 }
 
-void fill_stats(const KScal& k, dehaze_stats* st) {
+void fill_stats(const KScal& k, const dehaze_params& p, dehaze_stats* st) {
   st->outer = k.outer;
   st->converged = (k.converged && !k.nonfinite && !k.stalled) ? 1 : 0;
   st->inner = k.inner_total;
   st->applications = 2 * k.inner_total + k.res_evals;
   st->rel_residual = k.rel;
   st->rel_residual0 = k.rel0;
-  st->rel_residual_out = k.rel_out;
+  // a float64 output is the iterate itself
+  st->rel_residual_out = p.u_state == DEHAZE_U_F64 ? k.rel : k.rel_out;
   st->status = k.nonfinite ? DEHAZE_ENONFINITE : DEHAZE_OK;
   st->restarts = k.restarted;
   st->stalled = k.stalled;
@@ -421,11 +426,123 @@ int krylov_loop(Ctx& ctx, const KrylovBatch& b, const dehaze_params& p, KScal* h
     }
   }
   if ((rc = krylov_residual(b, kc, 1, s))) return rc;
-  // the float64 iterate is returned rounded to float32; its residual there
-  // is reported beside the iterate's own
-  if ((rc = krylov_residual(b, kc, 2, s))) return rc;
+  // the float64 iterate is returned rounded to float32 (unless the caller
+  // takes it in float64); its residual there is reported beside the
+  // iterate's own
+  if (p.u_state != DEHAZE_U_F64 && (rc = krylov_residual(b, kc, 2, s))) return rc;
   if (need_scalars || p.rel_tol > 0.0) return read_scalars(b, h, s);
   return DEHAZE_OK;
+}
+
+}  // namespace
+
+// Strip heights of the BiCGSTAB operator kernels per batch composition: the
+// key lists every image size with its count, the value the height of each
+// size.  Every height gives the same results (the dot products are summed per
+// block of kSBlk rows), so the choice only affects speed.
+struct KrylovTune {
+  std::map<std::vector<std::array<int, 3>>, std::map<std::pair<int, int>, int>> best;
+};
+
+namespace {
+
+constexpr int kKrylovRows[] = {16, 32, 64, 128, 256};
+
+std::vector<std::array<int, 3>> composition(const std::vector<KImg>& imgs) {
+  std::map<std::pair<int, int>, int> cnt;
+  for (const KImg& m : imgs) cnt[{m.H, m.W}] += 1;
+  std::vector<std::array<int, 3>> key;
+  for (const auto& [hw, c] : cnt) key.push_back({hw.first, hw.second, c});
+  return key;
+}
+
+// Sets the strip height of every image from its size; returns the wavefronts
+// of one launch.
+int lay_out(std::vector<KImg>& imgs, const std::map<std::pair<int, int>, int>& rows) {
+  int unit0 = 0;
+  for (KImg& m : imgs) {
+    m.us = rows.at({m.H, m.W});
+    m.nunits = krylov_units(m.H, m.W, m.us);
+    m.unit0 = unit0;
+    unit0 += m.nunits;
+  }
+  return unit0;
+}
+
+bool strips_usable(const std::vector<KImg>& imgs, const dehaze_params& p) {
+  if (p.g_radius != 2) return false;
+  for (const KImg& m : imgs)
+    if (!krylov_strips_fit(m.H, m.W)) return false;
+  return true;
+}
+
+// Strip heights by the size rule (or forced by krylov_rows), per image size.
+std::map<std::pair<int, int>, int> rule_rows(const std::vector<KImg>& imgs, const dehaze_params& p) {
+  const int n = static_cast<int>(imgs.size());
+  std::vector<int> hs(n), ws(n), us(n);
+  for (int i = 0; i < n; ++i) {
+    hs[i] = imgs[i].H;
+    ws[i] = imgs[i].W;
+  }
+  krylov_strip_rows(n, hs.data(), ws.data(), us.data());
+  std::map<std::pair<int, int>, int> rows;
+  for (int i = 0; i < n; ++i) rows[{hs[i], ws[i]}] = p.krylov_rows > 0 ? p.krylov_rows : us[i];
+  return rows;
+}
+
+// Chooses the strip height of every image of the launch and uploads the
+// descriptors and the wavefront map; b.nunits receives the launch's
+// wavefront count (0: the tile kernels run, when an image is too large for
+// the strip kernels' 32-bit offsets or R != 2).  Without krylov_rows, the
+// first solve of a batch composition times kernel (a) over the whole launch
+// for each candidate height of each image size in turn (sizes with the most
+// pixels first, the others held at their current choice), starting from the
+// size rule, and the context keeps the fastest.
+int choose_strips(Ctx& ctx, std::vector<KImg>& imgs, KrylovBatch& b, const dehaze_params& p, hipStream_t s) {
+  if (!strips_usable(imgs, p)) {
+    b.nunits = 0;
+    return DEHAZE_OK;
+  }
+  std::map<std::pair<int, int>, int> rows = rule_rows(imgs, p);
+  auto upload = [&]() -> int {
+    b.nunits = lay_out(imgs, rows);
+    return krylov_upload_strips(b, imgs.data(), s);
+  };
+  if (p.krylov_rows > 0) return upload();
+  if (!ctx.ktune) ctx.ktune = new KrylovTune();
+  const auto key = composition(imgs);
+  auto it = ctx.ktune->best.find(key);
+  if (it != ctx.ktune->best.end()) {
+    rows = it->second;
+    return upload();
+  }
+  const KConst kc = make_kconst(p);
+  int rc;
+  float best = 0.0f;
+  if ((rc = upload()) || (rc = krylov_time_strips(b, kc, 3, s, &best))) return rc;
+  std::vector<std::pair<long long, std::pair<int, int>>> order;
+  for (const auto& k : key) order.push_back({-static_cast<long long>(k[0]) * k[1] * k[2], {k[0], k[1]}});
+  std::sort(order.begin(), order.end());
+  for (const auto& [neg, hw] : order) {
+    const int keep = rows[hw];
+    int chosen = keep;
+    std::vector<int> seen{(hw.first + keep - 1) / keep};
+    for (int cand : kKrylovRows) {
+      const int strips = (hw.first + cand - 1) / cand;
+      if (std::find(seen.begin(), seen.end(), strips) != seen.end()) continue;
+      seen.push_back(strips);
+      rows[hw] = cand;
+      float t = 0.0f;
+      if ((rc = upload()) || (rc = krylov_time_strips(b, kc, 3, s, &t))) return rc;
+      if (t < best) {
+        best = t;
+        chosen = cand;
+      }
+    }
+    rows[hw] = chosen;
+  }
+  ctx.ktune->best[key] = rows;
+  return upload();
 }
 
 int image_status(const KScal& k, const dehaze_params& p) {
@@ -456,13 +573,18 @@ int run_krylov(Ctx& ctx, const SolveArgs& a, const dehaze_params& p, dehaze_stat
     u0 = pl.u0w;
   }
   if ((rc = krylov_init(b, &pl.img, &u0, s))) return rc;
+  std::vector<KImg> one{pl.img};
+  if ((rc = choose_strips(ctx, one, b, p, s))) return rc;
+  pl.img = one[0];
   KScal hs{};
   if ((rc = krylov_loop(ctx, b, p, &hs, st != nullptr, s))) return rc;
-  if ((rc = krylov_output(pl.img, a.u, s))) return rc;
+  rc = p.u_state == DEHAZE_U_F64 ? krylov_output64(pl.img, reinterpret_cast<double*>(a.u), s)
+                                 : krylov_output(pl.img, a.u, s);
+  if (rc) return rc;
   if (!st && p.rel_tol <= 0.0) return DEHAZE_OK;
   const int status = image_status(hs, p);
   if (st) {
-    fill_stats(hs, st);
+    fill_stats(hs, p, st);
     st->status = status;
     DZ_HIP(hipMemcpyAsync(st->A, a.A, 3 * sizeof(float), hipMemcpyDeviceToHost, s));
     DZ_HIP(hipStreamSynchronize(s));
@@ -511,12 +633,13 @@ BatchPlan plan_batch(void* ws, int n, const dehaze_image* im, const dehaze_param
     wsz[i] = im[i].W;
   }
   krylov_strip_rows(n, hs.data(), wsz.data(), us.data());
-  int tile0 = 0, unit0 = 0;
+  int tile0 = 0, unit0 = 0, blk0 = 0;
   for (int i = 0; i < n; ++i) {
     char* arena = cv.take<char>(krylov_image_bytes(im[i].H, im[i].W));
-    pl.imgs.push_back(krylov_carve(arena, im[i].H, im[i].W, tile0, unit0, us[i]));
+    pl.imgs.push_back(krylov_carve(arena, im[i].H, im[i].W, tile0, unit0, blk0, us[i]));
     tile0 += pl.imgs.back().ntiles;
     unit0 += pl.imgs.back().nunits;
+    blk0 += pl.imgs.back().nblk;
     const bool need_t = !im[i].t && !im[i].t_out;
     const bool need_A = !im[i].A && !im[i].A_out;
     pl.t_int.push_back(need_t ? cv.take<float>(static_cast<size_t>(im[i].H) * im[i].W) : nullptr);
@@ -529,8 +652,10 @@ BatchPlan plan_batch(void* ws, int n, const dehaze_image* im, const dehaze_param
   pl.d_scal = cv.take<KScal>(n);
   pl.d_tile_img = cv.take<int>(tile0);
   pl.d_part = cv.take<double>(static_cast<size_t>(kKPart) * tile0);
-  pl.d_unit_img = cv.take<int>(unit0);
-  pl.d_upart = cv.take<double>(static_cast<size_t>(kKPart) * unit0);
+  // room for the most strip wavefronts (kSBlk rows each), one partial-sum
+  // slot per block
+  pl.d_unit_img = cv.take<int>(blk0);
+  pl.d_upart = cv.take<double>(static_cast<size_t>(kKPart) * blk0);
   pl.bytes = cv.used();
   return pl;
 }
@@ -616,6 +741,30 @@ int sweep_shape(const Ctx& ctx, int H, int W, int scheme, int* K, int* S, int* C
   return DEHAZE_OK;
 }
 
+int batch_strip_rows(const Ctx* ctx, int n, const dehaze_image* im, const dehaze_params& p, int* rows, int* tuned) {
+  std::vector<KImg> imgs(n);
+  for (int i = 0; i < n; ++i) {
+    imgs[i] = KImg{};
+    imgs[i].H = im[i].H;
+    imgs[i].W = im[i].W;
+  }
+  *tuned = 0;
+  if (!strips_usable(imgs, p)) {
+    for (int i = 0; i < n; ++i) rows[i] = 0;
+    return DEHAZE_OK;
+  }
+  std::map<std::pair<int, int>, int> r = rule_rows(imgs, p);
+  if (p.krylov_rows <= 0 && ctx && ctx->ktune) {
+    auto it = ctx->ktune->best.find(composition(imgs));
+    if (it != ctx->ktune->best.end()) {
+      r = it->second;
+      *tuned = 1;
+    }
+  }
+  for (int i = 0; i < n; ++i) rows[i] = r.at({im[i].H, im[i].W});
+  return DEHAZE_OK;
+}
+
 size_t batch_workspace_bytes(int n, const dehaze_image* imgs, const dehaze_params& p) {
   return plan_batch(nullptr, n, imgs, p).bytes;
 }
@@ -635,10 +784,14 @@ int solve_batch(Ctx& ctx, int n, const dehaze_image* im, int dtype, int layout, 
   }
   KrylovBatch b{pl.d_imgs, pl.d_scal, pl.d_tile_img, pl.d_part, n, pl.ntiles, pl.d_unit_img, pl.d_upart, pl.nunits};
   if ((rc = krylov_init(b, pl.imgs.data(), u0.data(), s))) return rc;
+  if ((rc = choose_strips(ctx, pl.imgs, b, p, s))) return rc;
   std::vector<KScal> hs(n);
   if ((rc = krylov_loop(ctx, b, p, hs.data(), st != nullptr, s))) return rc;
-  for (int i = 0; i < n; ++i)
-    if ((rc = krylov_output(pl.imgs[i], im[i].u, s))) return rc;
+  for (int i = 0; i < n; ++i) {
+    rc = p.u_state == DEHAZE_U_F64 ? krylov_output64(pl.imgs[i], reinterpret_cast<double*>(im[i].u), s)
+                                   : krylov_output(pl.imgs[i], im[i].u, s);
+    if (rc) return rc;
+  }
   if (!st && p.rel_tol <= 0.0) return DEHAZE_OK;
   int worst = DEHAZE_OK;
   std::vector<float> Ah(3 * static_cast<size_t>(n));
@@ -649,7 +802,7 @@ int solve_batch(Ctx& ctx, int n, const dehaze_image* im, int dtype, int layout, 
     const int status = image_status(hs[i], p);
     if (status == DEHAZE_ENONFINITE || (status == DEHAZE_ENOTCONV && worst == DEHAZE_OK)) worst = status;
     if (st) {
-      fill_stats(hs[i], &st[i]);
+      fill_stats(hs[i], p, &st[i]);
       st[i].status = status;
       for (int c = 0; c < 3; ++c) st[i].A[c] = Ah[3 * i + c];
     }
@@ -662,6 +815,8 @@ int solve_batch(Ctx& ctx, int n, const dehaze_image* im, int dtype, int layout, 
 void solver_release(Ctx& ctx) {
   delete ctx.tune;
   ctx.tune = nullptr;
+  delete ctx.ktune;
+  ctx.ktune = nullptr;
   if (!ctx.graphs) return;
   if (ctx.graphs->exec) (void)hipGraphExecDestroy(ctx.graphs->exec);
   if (ctx.graphs->cap) (void)hipStreamDestroy(ctx.graphs->cap);

@@ -21,6 +21,9 @@ int solve_one(Ctx& ctx, const SolveArgs& a, const dehaze_params& p, dehaze_stats
 void solver_release(Ctx& ctx);
 int sweep_shape(const Ctx& ctx, int H, int W, int scheme, int* K, int* S, int* C);
 size_t batch_workspace_bytes(int n, const dehaze_image* imgs, const dehaze_params& p);
+// Strip height of the BiCGSTAB kernels for each image of a batch (0: the tile
+// kernels); *tuned = 1 when the context has timed this batch composition.
+int batch_strip_rows(const Ctx* ctx, int n, const dehaze_image* imgs, const dehaze_params& p, int* rows, int* tuned);
 int solve_batch(Ctx& ctx, int n, const dehaze_image* imgs, int dtype, int layout, const dehaze_params& p, void* ws,
                 dehaze_stats* st, hipStream_t s);
 

@@ -53,3 +53,35 @@ def test_host_validation_without_gpu():
     assert lib.dehaze_solve_workspace_size(0, 5, ctypes.byref(p)) == 0
     assert lib.dehaze_prior_workspace_size(64, 64, ctypes.byref(p)) > 10 * 64 * 64 * 4
     assert lib.dehaze_strerror(-4) == b"tolerance not reached"
+
+
+def test_krylov_strip_routing_matches_the_size_limit():
+    # Host-only query of the BiCGSTAB strip heights.  Every size the ABI
+    # accepts (H * W <= 2^30) either gets a strip height that keeps the strip
+    # kernels' 32-bit plane offsets in range, or routes the whole batch to the
+    # tile kernels (0).  No context: the size rule alone.
+    d = pytest.importorskip("paper_2506_08793_amd")
+    p = d.dehaze_params_default()
+    rows, tuned = d.dehaze_batch_strip_rows(None, [(1080, 1920), (256, 256), (2160, 3840)], p)
+    assert not tuned and all(r > 0 and r % 16 == 0 for r in rows)
+    assert rows[0] == 128 and rows[2] == 128 and rows[1] == 16
+    for H, W in [(1 << 15, 1 << 15), (1 << 14, 1 << 16), (1, 1 << 30), (1 << 30, 1), (16383, 32767)]:
+        assert H * W <= 1 << 30
+        fits = (H + 1) * (((W + 1 + 63) // 64) * 64) * 4 < 1 << 31
+        rows, _ = d.dehaze_batch_strip_rows(None, [(H, W), (64, 64)], p)
+        if fits:
+            assert rows[0] > 0 and rows[1] > 0
+        else:
+            assert rows == [0, 0], (H, W)          # one image too large: the batch runs the tile kernels
+    # forced height, and radius other than 2 (tile kernels)
+    assert d.dehaze_batch_strip_rows(None, [(100, 100)], p.replace(krylov_rows=48))[0] == [48]
+    assert d.dehaze_batch_strip_rows(None, [(100, 100)], p.replace(g_radius=1))[0] == [0]
+    lib = d.binding.lib()
+    import ctypes
+    img = (d.Image * 1)(d.Image(1, 8, 8, 8, 0, 1, None, None, None, None, None))
+    rows, tuned = (ctypes.c_int * 1)(), ctypes.c_int()
+    for bad in (8, 520, -16):
+        q = p.replace(krylov_rows=bad)
+        assert lib.dehaze_batch_strip_rows(None, 1, img, ctypes.byref(q), rows, ctypes.byref(tuned)) == d.binding.EINVAL
+    assert lib.dehaze_batch_strip_rows(None, 1, img, ctypes.byref(p.replace(u_state=2)), rows,
+                                       ctypes.byref(tuned)) == d.binding.EINVAL

@@ -113,7 +113,9 @@ def test_batch_images_progress_independently(warm):
     # Default settings (tick loop): each image keeps its own BiCGSTAB
     # iteration count, so an image of a batch goes through exactly the steps
     # it goes through alone, whatever the other images need.  Sizes chosen so
-    # that the images differ in outer steps and iterations per step.
+    # that the images differ in outer steps and iterations per step.  The
+    # strip height the batch's tuner picks for an image may differ from the
+    # one it gets alone; the results do not depend on it (next test).
     require_gpu()
     import paper_2506_08793_amd as d
     sizes = [(96, 128), (40, 31), (200, 150), (1, 1)]
@@ -128,3 +130,50 @@ def test_batch_images_progress_independently(warm):
         assert np.array_equal(host(u1[0]), host(us[k])), k
         for key in ("outer", "inner", "applications", "rel_residual", "rel_residual0", "converged", "restarts"):
             assert st1[0][key] == st[k][key], (k, key)
+
+
+def test_batch_float64_output():
+    # u_state = DEHAZE_U_F64: every image returns its float64 iterate, whose
+    # float32 rounding is the float32 output and whose residual the stats give
+    require_gpu()
+    import paper_2506_08793_amd as d
+    import torch
+    arrs, _ = _images([(24, 24), (40, 31), (17, 50)], 650)
+    imgs = [dev(a) for a in arrs]
+    p = d.dehaze_params_default(max_outer=4000, rel_tol=1e-5)
+    say("batch to 1e-5, float32 and float64 outputs")
+    u32, st32, _, _ = d.dehaze_batch(ctx(), imgs, params=p)
+    u64, st64, _, _ = d.dehaze_batch(ctx(), imgs, params=p.replace(u_state=d.U_F64))
+    for k in range(len(imgs)):
+        assert u64[k].dtype == torch.float64
+        assert np.array_equal(host(u64[k]).astype(np.float32), host(u32[k]))
+        assert st64[k]["converged"] and st64[k]["rel_residual_out"] == st64[k]["rel_residual"] <= 1e-5
+        assert st64[k]["rel_residual"] == st32[k]["rel_residual"]
+
+
+def test_strip_height_does_not_change_results():
+    # The BiCGSTAB strip kernels sum their dot products per block of 16 rows
+    # in a fixed order, so every strip height, forced or tuned, gives the same
+    # iterates bit for bit: several column groups, a ragged last strip, and a
+    # batch of uneven sizes.
+    require_gpu()
+    import paper_2506_08793_amd as d
+    sizes = [(300, 517), (40, 31), (129, 70)]
+    arrs, _ = _images(sizes, 900)
+    imgs = [dev(a) for a in arrs]
+    base = d.dehaze_params_default(max_outer=6, rel_tol=0.0)
+    ref = None
+    for rows in (16, 32, 48, 64, 128, 256, 0):
+        say(f"strip rows {rows}")
+        us, st, _, _ = d.dehaze_batch(ctx(), imgs, params=base.replace(krylov_rows=rows))
+        got = [host(u) for u in us]
+        if ref is None:
+            ref = (got, st)
+            continue
+        for k in range(len(sizes)):
+            assert np.array_equal(got[k], ref[0][k]), (rows, k)
+            for key in ("outer", "inner", "rel_residual", "rel_residual_out"):
+                assert st[k][key] == ref[1][k][key], (rows, k, key)
+    chosen, tuned = d.dehaze_batch_strip_rows(ctx(), sizes, base)
+    say(f"  tuned strip rows {chosen}")
+    assert tuned and all(r in (16, 32, 64, 128, 256) for r in chosen)

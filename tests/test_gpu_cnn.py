@@ -42,9 +42,39 @@ def test_forward_matches_oracle():
     err = np.max(np.abs(u - ref))
     scale = np.max(np.abs(ref))
     say(f"  max-abs {err:.3e} of max|u| {scale:.3f}; mean {np.mean(np.abs(u - ref)):.3e}")
-    assert err <= 2e-2 * scale
-    assert np.mean(np.abs(u - ref)) <= 2e-3 * scale
+    # measured 2.0e-3 * scale: activations stored in bf16 on both sides, so
+    # what remains is an occasional activation on the other side of a bf16
+    # rounding boundary (float32 versus float64 accumulation before it)
+    assert err <= 5e-3 * scale
+    assert np.mean(np.abs(u - ref)) <= 2e-4 * scale
     assert np.array_equal(d.dehaze_cnn_get_weights(ctx()), w)
+
+
+# unit roundoff of bfloat16 (8 significand bits)
+BF16_U = 2.0 ** -8
+
+
+def _rounding_variance(cache, params, gy):
+    """Variance of the error of every parameter gradient when, as on the GPU,
+    the back-propagated gradient is rounded to bfloat16 before each layer's
+    backward pass.  Each rounding adds an independent error uniform within
+    BF16_U of its value (variance BF16_U^2 g^2 / 3); errors propagate
+    linearly, so their variances travel through the same backward pass run on
+    squared weights and squared activations (Higham and Mary's probabilistic
+    rounding-error analysis).  Activations are bf16 on both sides, so their
+    rounding contributes nothing here."""
+    grads = [None] * len(params)
+    g, var = gy, np.zeros_like(gy)
+    for k in range(len(params) - 1, -1, -1):
+        h, z = cache[k]
+        if k != len(params) - 1:
+            g, var = g * (z > 0.0), var * (z > 0.0)
+        var = var + BF16_U * BF16_U / 3.0 * g * g
+        vdx, vW, vb = c.conv3x3_backward(h * h, params[k][0] ** 2, var)
+        dx, _, _ = c.conv3x3_backward(h, params[k][0], g)
+        grads[k] = (vW, vb)
+        g, var = dx, vdx
+    return c.flatten(grads)
 
 
 def test_gradients_match_oracle():
@@ -65,17 +95,21 @@ def test_gradients_match_oracle():
     loss_ref, gy = c.mse(y, target.astype(np.float64))
     grads = c.backward(cache, params, c.OUT_SCALE * gy)
     ref = c.flatten(grads)
+    sd = np.sqrt(_rounding_variance(cache, params, c.OUT_SCALE * gy))
     say(f"  loss gpu {loss:.6e} oracle {loss_ref:.6e}")
     assert abs(loss - loss_ref) <= 1e-2 * loss_ref
     off = 0
     for k, (ci, co) in enumerate(c.LAYERS):
         nW = ci * co * 9
         for name, sl in (("W", slice(off, off + nW)), ("b", slice(off + nW, off + nW + co))):
-            rel = np.linalg.norm(g[sl] - ref[sl]) / np.linalg.norm(ref[sl])
-            say(f"  layer {k} {name}: relative error {rel:.3e}")
-            # bf16 storage of the back-propagated gradient (8-bit mantissa,
-            # re-rounded at every layer) bounds the agreement to about 1e-2
-            assert rel <= 5e-2
+            err = np.abs(g[sl] - ref[sl])
+            # element by element: 8 standard deviations of the bf16 rounding
+            # error (a float64 emulation of the GPU's roundings stays under
+            # 0.32 of it), plus float32 accumulation far below that
+            bound = 8.0 * sd[sl] + 1e-6 * np.max(np.abs(ref[sl]))
+            say(f"  layer {k} {name}: max err/bound {np.max(err / bound):.3f}, "
+                f"relative norm {np.linalg.norm(g[sl] - ref[sl]) / np.linalg.norm(ref[sl]):.2e}")
+            assert np.all(err <= bound), (k, name, int(np.argmax(err / bound)))
         off += nW + co
 
 

@@ -2,6 +2,7 @@
 the oracle's exact Picard steps (sparse LU per step), on the same float32 t, A."""
 import numpy as np
 import pytest
+import torch
 
 import synth
 from gpu_util import ctx, dev, host, require_gpu, say, ulp32
@@ -192,3 +193,52 @@ def test_picard_full_size_1080p():
         f"after a half-ulp nudge {rho_nudged:.3e}")
     assert abs(rho - st["rel_residual_out"]) <= 1e-4 * rho + RHO_ABS
     assert st["rel_residual"] <= rho <= rho_nudged
+
+
+def test_picard_full_size_1080p_float64_output():
+    # The same workload with u returned in float64 (u_state = DEHAZE_U_F64):
+    # the caller now holds the iterate the tolerance was tested on, so the
+    # oracle's float64 residual of the returned u (on the float32 Phi and
+    # lambda the library formed) meets rel_tol and equals the reported value
+    # up to summation order; rounding it to float32 gives the float32 output.
+    require_gpu()
+    import paper_2506_08793_amd as d
+    img = synth.hazy_image(1080, 1920, 7000, beta_haze=(0.5, 2.5), occlusion=True)
+    say("picard 1080p to 1e-5, float64 output")
+    I = dev(img["I"])
+    pg = d.dehaze_prior(ctx(), I, outputs=("t",))
+    p64 = d.dehaze_params_default(u_state=d.U_F64)
+    u64, st = d.dehaze_solve(ctx(), I, pg["t"], pg["A"], params=p64)
+    say(f"  {st}")
+    assert u64.dtype == torch.float64
+    assert st["converged"] and st["rel_residual"] <= 1e-5 and st["rel_residual_out"] == st["rel_residual"]
+    t32, A32 = host(pg["t"]), host(pg["A"])
+    lam32 = o.adaptive_weight(t32.astype(np.float64)).astype(np.float32).astype(np.float64)
+    phi32 = o.reconstruction(img["I"], t32, A32, o.DEFAULT.t0).astype(np.float32).astype(np.float64)
+    _, rho = o.residual(host(u64), phi32, lam32)
+    say(f"  oracle rho of the float64 output {rho:.6e}, library {st['rel_residual']:.6e}")
+    assert rho <= 1e-5 * (1 + 1e-9)
+    assert abs(rho - st["rel_residual"]) <= 1e-9 * rho
+    u32, _ = d.dehaze_solve(ctx(), I, pg["t"], pg["A"], params=d.dehaze_params_default(), stats=False)
+    assert np.array_equal(host(u64).astype(np.float32), host(u32))
+
+
+@pytest.mark.parametrize("scheme", [1, 2])
+def test_float64_output_is_the_iterate(scheme):
+    # float32 output = the float64 output rounded (lagged diffusivity, whose
+    # iterate is float64); the sweep schemes iterate in float32 and widen it
+    require_gpu()
+    import paper_2506_08793_amd as d
+    I, t32, A32, lam, phi = _inputs(37, 53, 15, beta=(0.5, 2.0), occlusion=True)
+    kw = dict(scheme=scheme, max_outer=12, rel_tol=0.0)
+    say(f"float64 output scheme {scheme}")
+    u32, st32 = d.dehaze_solve(ctx(), dev(I), dev(t32), dev(A32), params=d.dehaze_params_default(**kw))
+    u64, st64 = d.dehaze_solve(ctx(), dev(I), dev(t32), dev(A32),
+                               params=d.dehaze_params_default(u_state=d.U_F64, **kw))
+    a32, a64 = host(u32), host(u64)
+    assert a64.dtype == np.float64
+    if scheme == 2:
+        assert np.array_equal(a64.astype(np.float32), a32)
+    else:
+        assert np.array_equal(a64, a32.astype(np.float64))
+    assert st64["rel_residual"] == st32["rel_residual"]
