@@ -138,7 +138,7 @@ def secondary(d, ctx, n: int, reps: int = 3) -> dict:
             "network": {"trained_on": f"{meta.get('images')} images {meta.get('size')}", "steps": meta.get("steps")}}
 
 
-def batch_workload(d, ctx, name: str) -> dict:
+def batch_workload(d, ctx, name: str, starts=(0, 2, 1)) -> dict:
     """Images/s of one dehaze_batch call to rho <= 1e-5: cold, analytic start, network-warm.
 
     batch64: 64 images of sizes drawn uniformly from {256x256, 640x480, 1280x720,
@@ -163,7 +163,7 @@ def batch_workload(d, ctx, name: str) -> dict:
     mpx = sum(h * w for h, w in sizes) / 1e6
     warmstart.load(ctx, warmstart.default_weights_path())
     out = {"workload": name, "images": len(sizes), "mpx": round(mpx, 2)}
-    for warm in (0, 2, 1):
+    for warm in starts:
         p = d.dehaze_params_default(max_outer=6000, rel_tol=1e-5, warm_start=warm)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -176,7 +176,11 @@ def batch_workload(d, ctx, name: str) -> dict:
             "outer_mean": float(np.mean([x["outer"] for x in st])), "outer_max": int(max(x["outer"] for x in st)),
             "converged": int(sum(x["converged"] for x in st)), "restarts": int(sum(x["restarts"] for x in st)),
             "rel_residual_max": float(max(x["rel_residual"] for x in st)),
-            "rel_residual_out_max": float(max(x["rel_residual_out"] for x in st))}
+            "rel_residual_out_max": float(max(x["rel_residual_out"] for x in st)),
+            # every image that did not reach the tolerance, by seed and size
+            "not_converged": [{"seed": base + k, "H": sizes[k][0], "W": sizes[k][1], "outer": x["outer"],
+                               "rel_residual": x["rel_residual"], "stalled": x["stalled"]}
+                              for k, x in enumerate(st) if not x["converged"]]}
         key = ("cold", "warm", "analytic")[warm]
         print(f"[bench] {name} {key}: {out[key]}", file=sys.stderr,
               flush=True)
@@ -207,6 +211,8 @@ def main() -> int:
     ap.add_argument("--sweeps-per-launch", type=int, default=0, help="pin K (default: the library's tuner)")
     ap.add_argument("--strip-rows", type=int, default=0, help="pin the strip height S (default: tuned)")
     ap.add_argument("--lane-columns", type=int, default=0, help="pin the columns per lane C (default: tuned)")
+    ap.add_argument("--starts", default="cold,analytic,warm",
+                    help="batch workloads: comma-separated starts to run (cold, analytic, warm)")
     ap.add_argument("--workload", choices=("jacobi1024", "batch64", "serving"), default="jacobi1024",
                     help="jacobi1024: the headline (default); batch64 / serving: images/s of the batched "
                          "lagged-diffusivity solve to rho 1e-5, printed as a JSON line of its own")
@@ -222,7 +228,8 @@ def main() -> int:
 
     ctx = d.Context(0)
     if args.workload != "jacobi1024":
-        print(json.dumps(batch_workload(d, ctx, args.workload)), flush=True)
+        starts = tuple({"cold": 0, "warm": 1, "analytic": 2}[k] for k in args.starts.split(","))
+        print(json.dumps(batch_workload(d, ctx, args.workload, starts)), flush=True)
         return 0
     img = synth.megapixel_image()
     I = torch.from_numpy(img["I"]).cuda()

@@ -126,7 +126,12 @@ typedef struct dehaze_params {
                                solves, R = 2): a multiple of 16 up to 512; 0 = time the candidates on the
                                first solve of each batch composition (synchronises) and keep the fastest
                                in the context.  Every value gives bit-identical results */
-  int32_t reserved[2];      /* must be zero */
+  int32_t ngmres_depth;     /* lagged-diffusivity solves: 0 = the plain iteration; 1..8 = accelerate it by
+                               nonlinear GMRES over that many earlier iterates (each outer step mixes the
+                               current iterate with them to minimise the linearised residual, then takes
+                               the lagged-diffusivity correction from the mix; same fixed point).  Needs
+                               inner_refine = 0; the workspace grows by 36 bytes per pixel and depth */
+  int32_t reserved[1];      /* must be zero */
 } dehaze_params;
 
 typedef struct dehaze_stats {

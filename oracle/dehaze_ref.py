@@ -42,6 +42,10 @@ Readings taken where the paper is silent or ambiguous (all are parameters):
   * Three iterations share the fixed point r(u) = 0: the paper's explicit
     relaxed update, a diagonally scaled (Jacobi) form of it, and the
     lagged-diffusivity (Picard) iteration u_{n+1} = L(D(u_n))^-1 Phi.
+  * Outer acceleration of the lagged-diffusivity iteration (not in the
+    paper, which leaves the iteration count open): nonlinear GMRES in the
+    sense of Washio and Oosterlee, with the Picard step as its
+    preconditioner (ngmres_solve).  It has the same fixed point.
 """
 from __future__ import annotations
 
@@ -486,6 +490,81 @@ def solve(phi, lam, scheme: str, p: Params = DEFAULT, steps: int = None,
         u = step(u, phi, lam, p)
         n += 1
     res.u, res.steps = u, n
+    return res
+
+
+def ngmres_mix(ut, rt, U, R, reg: float = 1e-10):
+    """Least-squares mixing of a trial iterate with earlier ones.
+
+    Given the trial iterate ut with its residual rt and earlier trial iterates
+    U[j] with residuals R[j], the coefficients b minimise
+    || rt + sum_j b_j (rt - R[j]) ||_2 (over all channels and pixels); they
+    solve the normal equations with a Tikhonov shift of reg * trace / n on
+    the diagonal, which only matters when the differences are nearly
+    dependent.  Returns (u_mix, r_mix, b): the mixed iterate
+    ut + sum_j b_j (ut - U[j]) and the same combination of the residuals (the
+    residual of u_mix to first order).
+    """
+    n = len(U)
+    if n == 0:
+        return np.array(ut, dtype=np.float64), np.array(rt, dtype=np.float64), np.zeros(0)
+    ut = np.asarray(ut, dtype=np.float64)
+    rt = np.asarray(rt, dtype=np.float64)
+    A = np.stack([(rt - np.asarray(Rj, dtype=np.float64)).reshape(-1) for Rj in R], axis=1)
+    G = A.T @ A
+    h = A.T @ rt.reshape(-1)
+    G = G + reg * np.trace(G) / n * np.eye(n)
+    b = np.linalg.solve(G, -h)
+    u_mix = ut + sum(bj * (ut - np.asarray(Uj, dtype=np.float64)) for bj, Uj in zip(b, U))
+    r_mix = rt + sum(bj * (rt - np.asarray(Rj, dtype=np.float64)) for bj, Rj in zip(b, R))
+    return u_mix, r_mix, b
+
+
+def ngmres_solve(phi, lam, p: Params = DEFAULT, depth: int = 5, steps: int = None, rel_tol: float = None,
+                 u0=None, max_steps: int = 100000, growth: float = 2.0) -> SolveResult:
+    """Lagged-diffusivity iteration accelerated by nonlinear GMRES.
+
+    Step n starts from the trial iterate ut_n and its residual r(ut_n):
+      1. mix ut_n with the last `depth` trial iterates (ngmres_mix), giving
+         u_mix and the combined residual r_mix;
+      2. take the lagged-diffusivity correction from u_mix with D frozen at
+         ut_n: ut_{n+1} = u_mix + L(D(ut_n))^-1 r_mix (exact sparse LU);
+      3. evaluate r(ut_{n+1}); if rho grows beyond `growth` times the lowest
+         rho so far, the history is dropped (the next step is a plain one).
+    With depth = 0 this is the lagged-diffusivity iteration itself:
+    ut + L(D(ut))^-1 (Phi - L(D(ut)) ut) = L(D(ut))^-1 Phi.  rho is recorded
+    for every trial iterate; the result is the last one.
+    """
+    w = gaussian_taps(p.sigma, p.g_radius)
+    phi = np.asarray(phi, dtype=np.float64)
+    ut = np.array(phi if u0 is None else u0, dtype=np.float64)
+    r, rho = residual(ut, phi, lam, p)
+    res = SolveResult(u=ut, rho=[rho])
+    U, R = [], []
+    best = rho
+    n = 0
+    limit = steps if steps is not None else max_steps
+    while not ((rel_tol is not None and rho <= rel_tol) or n >= limit):
+        u_mix, r_mix, _ = ngmres_mix(ut, r, U, R)
+        if depth > 0:
+            U.append(ut.copy())
+            R.append(r.copy())
+            if len(U) > depth:
+                U.pop(0)
+                R.pop(0)
+        Dx, Dy = face_coefficients(ut, p)
+        delta = np.empty_like(ut)
+        for c in range(ut.shape[0]):
+            L = assemble_operator(Dx[c], Dy[c], lam, w, p).tocsc()
+            delta[c] = spla.splu(L, permc_spec="MMD_AT_PLUS_A").solve(r_mix[c].reshape(-1)).reshape(ut.shape[1:])
+        ut = u_mix + delta
+        r, rho = residual(ut, phi, lam, p)
+        res.rho.append(rho)
+        n += 1
+        if rho > growth * best:
+            U, R = [], []
+        best = min(best, rho)
+    res.u, res.steps = ut, n
     return res
 
 

@@ -35,7 +35,8 @@ class Params(ctypes.Structure):
         ("adaptive", c_int32), ("edge_preserving", c_int32), ("sweeps_per_launch", c_int32),
         ("inner_refine", c_int32), ("strip_rows", c_int32), ("lane_columns", c_int32),
         ("stall_window", c_int32), ("guided_radius", c_int32), ("dark_scales", c_int32),
-        ("guided_eps", c_double), ("u_state", c_int32), ("krylov_rows", c_int32), ("reserved", c_int32 * 2),
+        ("guided_eps", c_double), ("u_state", c_int32), ("krylov_rows", c_int32),
+        ("ngmres_depth", c_int32), ("reserved", c_int32 * 1),
     ]
 
     def replace(self, **kw) -> "Params":

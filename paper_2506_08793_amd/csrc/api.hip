@@ -69,6 +69,11 @@ int check_params(const dehaze_params* p) {
     set_error("krylov_rows must be 0 or a multiple of 16 up to 512");
     return DEHAZE_EINVAL;
   }
+  if (p->ngmres_depth < 0 || p->ngmres_depth > 8) { set_error("ngmres_depth must lie in 0..8"); return DEHAZE_EINVAL; }
+  if (p->ngmres_depth > 0 && p->inner_refine > 0) {
+    set_error("ngmres_depth needs inner_refine = 0");
+    return DEHAZE_EINVAL;
+  }
   if (p->u_state != DEHAZE_U_F32 && p->u_state != DEHAZE_U_F64) {
     set_error("u_state must be DEHAZE_U_F32 or DEHAZE_U_F64");
     return DEHAZE_EINVAL;

@@ -38,6 +38,7 @@ KConst make_kconst(const dehaze_params& p) {
   c.stall_window = p.stall_window;
   c.max_inner = p.max_inner;
   c.max_outer = p.max_outer;
+  c.ng_m = p.ngmres_depth;
   return c;
 }
 
@@ -81,7 +82,7 @@ struct KCarve {
   size_t bytes;
 };
 
-KCarve carve(void* base, int H, int W, int tile0, int unit0, int blk0, int us) {
+KCarve carve(void* base, int H, int W, int tile0, int unit0, int blk0, int us, int ng_m) {
   KCarve k{};
   const int P = padded_pitch(W + 1);
   const size_t plane = static_cast<size_t>(H) * P;
@@ -116,6 +117,8 @@ KCarve carve(void* base, int H, int W, int tile0, int unit0, int blk0, int us) {
   m.s = cv.take<float>(3 * plane);
   m.t = cv.take<float>(3 * plane);
   m.x = cv.take<float>(3 * plane);
+  m.Uh = ng_m > 0 ? cv.take<double>(3 * plane * ng_m) : nullptr;
+  m.Rh = ng_m > 0 ? cv.take<float>(3 * plane * ng_m) : nullptr;
   k.bytes = cv.used();
   return k;
 }
@@ -163,23 +166,23 @@ __device__ __forceinline__ void block_sum(double (&v)[N]) {
 }
 
 // Writes this tile's N partial sums (block sum; thread 0 stores them).
-template <int N>
+template <int N, int STRIDE = kKPart>
 __device__ __forceinline__ void write_partials(double (&v)[N], double* part, int gtile) {
   block_sum<N>(v);
   if (threadIdx.x == 0)
-    for (int k = 0; k < N; ++k) part[static_cast<size_t>(gtile) * kKPart + k] = v[k];
+    for (int k = 0; k < N; ++k) part[static_cast<size_t>(gtile) * STRIDE + k] = v[k];
 }
 
 // Image totals of the tile partials, summed over tiles in index order with a
 // fixed assignment to threads and a fixed tree; valid in thread 0.  Run by
 // the per-image reduction kernels (one workgroup per image) after the kernel
 // that wrote the partials, so plain loads see them.
-template <int N, bool UNITS = false>
+template <int N, bool UNITS = false, int STRIDE = kKPart>
 __device__ __forceinline__ void image_sums(const KImg& I, const double* part, double (&tot)[N]) {
   for (int k = 0; k < N; ++k) tot[k] = 0.0;
   const int n = UNITS ? I.nblk : I.ntiles, first = UNITS ? I.blk0 : I.tile0;
   for (int q = threadIdx.x; q < n; q += NT)
-    for (int k = 0; k < N; ++k) tot[k] += part[static_cast<size_t>(first + q) * kKPart + k];
+    for (int k = 0; k < N; ++k) tot[k] += part[static_cast<size_t>(first + q) * STRIDE + k];
   block_sum<N>(tot);
 }
 
@@ -402,6 +405,9 @@ __global__ __launch_bounds__(NT) void k_red_res(const KImg* __restrict__ imgs, K
         sc->restart = 0;
         sc->best = sc->mark = rel;
         sc->since = 0;
+        sc->ng_nh = 0;
+        sc->ng_slot = 0;
+        sc->ng_best = rel;
       } else if (kc.stall_window > 0) {
         sc->best = fmin(sc->best, rel);
         if (++sc->since >= kc.stall_window) {
@@ -433,8 +439,22 @@ __global__ __launch_bounds__(NT) void k_red_res(const KImg* __restrict__ imgs, K
     sc->it = 1;
     // no inner solve on a step that decided a restart (the next residual pass
     // replaces the iterate), nor once the iteration stops
-    sc->inner_done =
-        (tot[2] > 0.0 && isfinite(tot[2]) && !sc->restart && !sc->converged && !sc->exhausted) ? 0 : 1;
+    const bool go = tot[2] > 0.0 && isfinite(tot[2]) && !sc->restart && !sc->converged && !sc->exhausted;
+    sc->inner_done = go ? 0 : 1;
+    if (!LINEAR && kc.ng_m > 0) {
+      // nonlinear GMRES: the mix comes first and starts the inner solve; a
+      // trial rho above twice the lowest since the last drop drops the history
+      sc->ng_pending = go ? 1 : 0;
+      sc->inner_done = 1;
+      if (go && sc->res_evals > 1) {
+        if (sc->rel > 2.0 * sc->ng_best) {
+          sc->ng_nh = 0;
+          sc->ng_drops += 1;
+          sc->ng_best = sc->rel;
+        }
+        sc->ng_best = fmin(sc->ng_best, sc->rel);
+      }
+    }
   }
 }
 
@@ -646,22 +666,29 @@ __global__ __launch_bounds__(NT) void k_red_b(const KImg* __restrict__ imgs, KSc
 }
 
 // ------------------------------------------------------------ BiCGSTAB, strips
+// Depth of the strip kernels' load rings (rows in flight per wavefront + 1).
+constexpr int kRing = 4;
+
 // The operator kernels (a) and (b) for the radius-2 Gaussian as register-
 // resident strip walks: one wavefront per (image, channel, group of kUOW
 // columns, strip of I.us rows); lane = column with a 2-column halo on each
 // side, horizontal neighbours by DPP shifts, vertical ones in 4-row windows.
 // Step r of the walk forms f = M^-1 q at input row r (q = p in (a), s in (b))
 // and applies the operator at row j = r - 2.  Loads go through buffer
-// resources with scalar row offsets, three rows ahead into 4-slot rings.
+// resources with scalar row offsets, RING - 1 rows ahead into RING-slot
+// rings (RING divides kSBlk).
 // MODE 0 is (a): p = r + beta (p - omega v); v = L M^-1 p; partial (rhat, v).
 // MODE 1 is (b): s = r - alpha v; t = L M^-1 s; partials (t, s), (t, t), (s, s).
-template <int MODE, bool FIRST>
+template <int MODE, bool FIRST, int RING>
 __global__ __launch_bounds__(256) void k_bicg_strip(const KImg* __restrict__ imgs, KScal* scal,
                                                      const int* __restrict__ unit_img, double* upart, KConst kc,
                                                      int nunits) {
 #pragma clang fp contract(off)
   constexpr int NACC = MODE == 0 ? 1 : 3;  // dot products: (rhat, v); (t, s), (t, t), (s, s)
-  constexpr int RING = 4, AHEAD = 3;
+  constexpr int AHEAD = RING - 1;
+  constexpr int HEAD = 4;                  // steps that fill the 4-row windows
+  static_assert(kSBlk % RING == 0 && RING >= HEAD, "RING must divide kSBlk and cover the head");
+  constexpr int TPB = kSBlk / RING;        // loop trips per block of kSBlk output rows
   const int gw = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (gw >= nunits) return;
   // uniform per wavefront: keeps the descriptor and everything from it scalar
@@ -790,20 +817,19 @@ __global__ __launch_bounds__(256) void k_bicg_strip(const KImg* __restrict__ img
     }
   };
   // head: rows y0 - 2 .. y0 + 1 fill the windows; then rows j = y0 .. y1 - 1,
-  // four per loop trip, a block complete after every fourth trip (y0 is a
-  // multiple of kSBlk = 16)
-  static_assert(kSBlk == 4 * RING, "one partial-sum block per four loop trips");
+  // RING per loop trip, a block complete after every TPB trips (y0 is a
+  // multiple of kSBlk); row r always sits in slot (r - rs0) % RING
   int r = rs0;
 #pragma unroll
-  for (int q = 0; q < RING; ++q) step(r + q, q, false);
-  r += RING;
+  for (int q = 0; q < HEAD; ++q) step(r + q, q, false);
+  r += HEAD;
   int trips = 0;
   for (; r - 2 < y1; r += RING) {
 #pragma unroll
-    for (int q = 0; q < RING; ++q) step(r + q, q, true);
-    if ((++trips & 3) == 0) flush(y0 / kSBlk + (trips >> 2) - 1);
+    for (int i = 0; i < RING; ++i) step(r + i, (HEAD + i) % RING, true);
+    if (++trips % TPB == 0) flush(y0 / kSBlk + trips / TPB - 1);
   }
-  if (trips & 3) flush(y0 / kSBlk + (trips >> 2));
+  if (trips % TPB) flush(y0 / kSBlk + trips / TPB);
 }
 
 // (c) x += alpha M^-1 p + omega M^-1 s; r = s - omega t; rho = (rhat, r); beta.
@@ -918,6 +944,190 @@ __global__ __launch_bounds__(NT) void k_update(const KImg* __restrict__ imgs, co
     }
 }
 
+// ------------------------------------------------------------ nonlinear GMRES
+// Gram sums of the residual differences d_j = r - R_j (r the trial residual,
+// float32, in rhat): (d_j, d_l) for j <= l < nh and (d_j, r), summed in
+// float64 per tile.  Four pixels of one row per thread, 16-byte accesses.
+template <int M>
+__global__ __launch_bounds__(NT) void k_ngm_dots(const KImg* __restrict__ imgs, const KScal* __restrict__ scal,
+                                                  const int* __restrict__ tile_img, double* npart) {
+  constexpr int NG = M * (M + 1) / 2 + M;
+  const int g = blockIdx.x;
+  const int im = tile_img[g];
+  const KImg I = imgs[im];
+  const KScal* sc = scal + im;
+  const int nh = sc->ng_nh;
+  if (sc->converged || !sc->ng_pending || nh == 0) return;
+  const TilePos tp = tile_pos(I, im, g);
+  const int ly = threadIdx.x >> 4, lx = (threadIdx.x & 15) * 4;
+  const int gy = tp.y0 + ly, gx = tp.x0 + lx;
+  const size_t plane = static_cast<size_t>(I.H) * I.P;
+  double acc[NG];
+  for (int k = 0; k < NG; ++k) acc[k] = 0.0;
+  if (gy < I.H && gx < I.W) {
+    const int nv = min(4, I.W - gx);
+    for (int c = 0; c < 3; ++c) {
+      const size_t e = c * plane + static_cast<size_t>(gy) * I.P + gx;
+      const float4 r4 = *reinterpret_cast<const float4*>(I.rhat + e);
+      const float rv[4] = {r4.x, r4.y, r4.z, r4.w};
+      float d[M][4];
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        if (j < nh) {
+          const float4 h4 = *reinterpret_cast<const float4*>(I.Rh + static_cast<size_t>(j) * 3 * plane + e);
+          d[j][0] = rv[0] - h4.x;
+          d[j][1] = rv[1] - h4.y;
+          d[j][2] = rv[2] - h4.z;
+          d[j][3] = rv[3] - h4.w;
+        } else {
+          d[j][0] = d[j][1] = d[j][2] = d[j][3] = 0.0f;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (q >= nv) break;
+        int k = 0;
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+#pragma unroll
+          for (int l = j; l < M; ++l) acc[k++] += static_cast<double>(d[j][q]) * d[l][q];
+          acc[M * (M + 1) / 2 + j] += static_cast<double>(d[j][q]) * rv[q];
+        }
+      }
+    }
+  }
+  write_partials<NG, kNPart>(acc, npart, g);
+}
+
+// Per image: the mixing coefficients b solve (A + s I) b = -h, A the Gram
+// matrix of the nh residual differences, h their products with r, s = 1e-10
+// trace(A) / nh; Gaussian elimination with partial pivoting in float64.  A
+// system that cannot be solved, or a non-finite b, gives b = 0 (a plain step).
+template <int M>
+__global__ __launch_bounds__(NT) void k_red_ngm(const KImg* __restrict__ imgs, KScal* scal, const double* npart) {
+  constexpr int NG = M * (M + 1) / 2 + M;
+  const int im = blockIdx.x;
+  const KImg I = imgs[im];
+  KScal* sc = scal + im;
+  const int nh = sc->ng_nh;
+  if (sc->converged || !sc->ng_pending || nh == 0) return;
+  double tot[NG];
+  image_sums<NG, false, kNPart>(I, npart, tot);
+  if (threadIdx.x != 0) return;
+  double A[M][M + 1];
+  int k = 0;
+  for (int j = 0; j < M; ++j) {
+    for (int l = j; l < M; ++l) {
+      A[j][l] = A[l][j] = tot[k];
+      ++k;
+    }
+    A[j][M] = -tot[M * (M + 1) / 2 + j];
+  }
+  double tr = 0.0;
+  for (int j = 0; j < nh; ++j) tr += A[j][j];
+  for (int j = 0; j < nh; ++j) A[j][j] += 1e-10 * tr / nh;
+  bool ok = tr > 0.0 && isfinite(tr);
+  for (int col = 0; col < nh && ok; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < nh; ++r)
+      if (fabs(A[r][col]) > fabs(A[piv][col])) piv = r;
+    if (!(fabs(A[piv][col]) > 0.0)) {
+      ok = false;
+      break;
+    }
+    if (piv != col)
+      for (int q = col; q <= M; ++q) {
+        const double t = A[col][q];
+        A[col][q] = A[piv][q];
+        A[piv][q] = t;
+      }
+    for (int r = col + 1; r < nh; ++r) {
+      const double f = A[r][col] / A[col][col];
+      for (int q = col; q < nh; ++q) A[r][q] -= f * A[col][q];
+      A[r][M] -= f * A[col][M];
+    }
+  }
+  double b[M];
+  for (int j = nh - 1; j >= 0 && ok; --j) {
+    double s = A[j][M];
+    for (int q = j + 1; q < nh; ++q) s -= A[j][q] * b[q];
+    b[j] = s / A[j][j];
+    ok = isfinite(b[j]);
+  }
+  for (int j = 0; j < M; ++j) sc->ngb[j] = (ok && j < nh) ? b[j] : 0.0;
+}
+
+// u_mix = ut + sum_j b_j (ut - U_j), r_mix = r + sum_j b_j (r - R_j); (ut, r)
+// goes into history slot ng_slot first.  Partial sum of r_mix^2 (the inner
+// solve's reference norm).
+template <int M>
+__global__ __launch_bounds__(NT) void k_ngm_mix(const KImg* __restrict__ imgs, const KScal* __restrict__ scal,
+                                                 const int* __restrict__ tile_img, double* part) {
+  const int g = blockIdx.x;
+  const int im = tile_img[g];
+  const KImg I = imgs[im];
+  const KScal* sc = scal + im;
+  if (sc->converged || !sc->ng_pending) return;
+  const int nh = sc->ng_nh, slot = sc->ng_slot;
+  double bj[M];
+  for (int j = 0; j < M; ++j) bj[j] = j < nh ? sc->ngb[j] : 0.0;
+  const TilePos tp = tile_pos(I, im, g);
+  const int tid = threadIdx.x, tx = tid & (kKTX - 1), ty = tid / kKTX;
+  const int gx = tp.x0 + tx;
+  const size_t plane = static_cast<size_t>(I.H) * I.P;
+  double acc[1] = {0.0};
+  for (int c = 0; c < 3; ++c)
+    for (int k = 0; k < kPixPerThread; ++k) {
+      const int gy = tp.y0 + ty + 4 * k;
+      if (gx < I.W && gy < I.H) {
+        const size_t e = c * plane + static_cast<size_t>(gy) * I.P + gx;
+        const double ut = I.u[e];
+        const float rt = I.rhat[e];
+        double um = ut, rm = rt;
+#pragma unroll
+        for (int j = 0; j < M; ++j)
+          if (j < nh) {
+            const size_t h = static_cast<size_t>(j) * 3 * plane + e;
+            um += bj[j] * (ut - I.Uh[h]);
+            rm += bj[j] * static_cast<double>(rt - I.Rh[h]);
+          }
+        const size_t hs = static_cast<size_t>(slot) * 3 * plane + e;
+        I.Uh[hs] = ut;
+        I.Rh[hs] = rt;
+        I.u[e] = um;
+        const float r32 = static_cast<float>(rm);
+        I.rhat[e] = r32;
+        acc[0] += static_cast<double>(r32) * r32;
+      }
+    }
+  write_partials<1>(acc, part, g);
+}
+
+// Starts the inner solve on the mixed right-hand side and advances the
+// history ring.
+__global__ __launch_bounds__(NT) void k_red_mix(const KImg* __restrict__ imgs, KScal* scal, const double* part,
+                                                 KConst kc) {
+  const int im = blockIdx.x;
+  const KImg I = imgs[im];
+  KScal* sc = scal + im;
+  if (sc->converged || !sc->ng_pending) return;
+  double tot[1];
+  image_sums<1>(I, part, tot);
+  if (threadIdx.x != 0) return;
+  sc->ng_pending = 0;
+  sc->ng_slot = (sc->ng_slot + 1) % kc.ng_m;
+  sc->ng_nh = min(sc->ng_nh + 1, kc.ng_m);
+  sc->bnorm2 = tot[0];
+  sc->rho = tot[0];
+  sc->alpha = 1.0;
+  sc->omega = 1.0;
+  sc->beta = 0.0;
+  sc->half_done = 0;
+  sc->pass_inner = 0;
+  sc->it = 1;
+  sc->inner_done = (tot[0] > 0.0 && isfinite(tot[0])) ? 0 : 1;
+}
+
 #define DZ_KRYLOV_DISPATCH(R_, LAUNCH) \
   switch (R_) {                        \
     case 0: LAUNCH(0); break;          \
@@ -930,10 +1140,10 @@ __global__ __launch_bounds__(NT) void k_update(const KImg* __restrict__ imgs, co
 
 }  // namespace
 
-size_t krylov_image_bytes(int H, int W) { return carve(nullptr, H, W, 0, 0, 0, 32).bytes; }
+size_t krylov_image_bytes(int H, int W, int ng_m) { return carve(nullptr, H, W, 0, 0, 0, 32, ng_m).bytes; }
 
-KImg krylov_carve(void* base, int H, int W, int tile0, int unit0, int blk0, int us) {
-  return carve(base, H, W, tile0, unit0, blk0, us).img;
+KImg krylov_carve(void* base, int H, int W, int tile0, int unit0, int blk0, int us, int ng_m) {
+  return carve(base, H, W, tile0, unit0, blk0, us, ng_m).img;
 }
 
 int krylov_upload_strips(const KrylovBatch& b, const KImg* h_imgs, hipStream_t s) {
@@ -1006,7 +1216,7 @@ int krylov_time_strips(const KrylovBatch& b, const KConst& c, int reps, hipStrea
   // one untimed launch first: caches, clocks
   for (int i = 0; i <= reps && rc == DEHAZE_OK; ++i) {
     if (i == 1 && hipEventRecord(e0, s) != hipSuccess) rc = DEHAZE_EHIP;
-    hipLaunchKernelGGL((k_bicg_strip<0, false>), ug, dim3(256), 0, s, b.d_imgs, b.d_scal, b.d_unit_img, b.d_upart, t,
+    hipLaunchKernelGGL((k_bicg_strip<0, false, kRing>), ug, dim3(256), 0, s, b.d_imgs, b.d_scal, b.d_unit_img, b.d_upart, t,
                        b.nunits);
     if (hipGetLastError() != hipSuccess) rc = DEHAZE_EHIP;
   }
@@ -1030,18 +1240,18 @@ int krylov_inner(const KrylovBatch& b, const KConst& c, hipStream_t s) {
   // beside the others
   if (c.R == 2 && b.nunits > 0) {
     const dim3 ug((b.nunits + 3) / 4);
-    hipLaunchKernelGGL((k_bicg_strip<0, true>), ug, dim3(256), 0, s, b.d_imgs, b.d_scal, b.d_unit_img, b.d_upart, c,
+    hipLaunchKernelGGL((k_bicg_strip<0, true, kRing>), ug, dim3(256), 0, s, b.d_imgs, b.d_scal, b.d_unit_img, b.d_upart, c,
                        b.nunits);
     DZ_CHECK_LAUNCH();
-    hipLaunchKernelGGL((k_bicg_strip<0, false>), ug, dim3(256), 0, s, b.d_imgs, b.d_scal, b.d_unit_img, b.d_upart, c,
+    hipLaunchKernelGGL((k_bicg_strip<0, false, kRing>), ug, dim3(256), 0, s, b.d_imgs, b.d_scal, b.d_unit_img, b.d_upart, c,
                        b.nunits);
     DZ_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_red_a<true>, dim3(b.nimg), dim3(NT), 0, s, b.d_imgs, b.d_scal, b.d_upart);
     DZ_CHECK_LAUNCH();
-    hipLaunchKernelGGL((k_bicg_strip<1, true>), ug, dim3(256), 0, s, b.d_imgs, b.d_scal, b.d_unit_img, b.d_upart, c,
+    hipLaunchKernelGGL((k_bicg_strip<1, true, kRing>), ug, dim3(256), 0, s, b.d_imgs, b.d_scal, b.d_unit_img, b.d_upart, c,
                        b.nunits);
     DZ_CHECK_LAUNCH();
-    hipLaunchKernelGGL((k_bicg_strip<1, false>), ug, dim3(256), 0, s, b.d_imgs, b.d_scal, b.d_unit_img, b.d_upart, c,
+    hipLaunchKernelGGL((k_bicg_strip<1, false, kRing>), ug, dim3(256), 0, s, b.d_imgs, b.d_scal, b.d_unit_img, b.d_upart, c,
                        b.nunits);
     DZ_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_red_b<true>, dim3(b.nimg), dim3(NT), 0, s, b.d_imgs, b.d_scal, b.d_upart, c);
@@ -1067,6 +1277,38 @@ int krylov_inner(const KrylovBatch& b, const KConst& c, hipStream_t s) {
   hipLaunchKernelGGL(k_red_c, dim3(b.nimg), dim3(NT), 0, s, b.d_imgs, b.d_scal, b.d_part, c);
   DZ_CHECK_LAUNCH();
   return DEHAZE_OK;
+}
+
+template <int M>
+int launch_ngmres(const KrylovBatch& b, const KConst& c, hipStream_t s) {
+  hipLaunchKernelGGL(k_ngm_dots<M>, dim3(b.ntiles), dim3(NT), 0, s, b.d_imgs, b.d_scal, b.d_tile_img, b.d_npart);
+  DZ_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_red_ngm<M>, dim3(b.nimg), dim3(NT), 0, s, b.d_imgs, b.d_scal, b.d_npart);
+  DZ_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_ngm_mix<M>, dim3(b.ntiles), dim3(NT), 0, s, b.d_imgs, b.d_scal, b.d_tile_img, b.d_part);
+  DZ_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_red_mix, dim3(b.nimg), dim3(NT), 0, s, b.d_imgs, b.d_scal, b.d_part, c);
+  DZ_CHECK_LAUNCH();
+  return DEHAZE_OK;
+}
+
+int krylov_ngmres(const KrylovBatch& b, const KConst& c, hipStream_t s) {
+  if (c.ng_m <= 0) return DEHAZE_OK;
+  if (!b.d_npart) {
+    set_error("nonlinear GMRES buffers missing");
+    return DEHAZE_EINVAL;
+  }
+  switch (c.ng_m) {
+    case 1: return launch_ngmres<1>(b, c, s);
+    case 2: return launch_ngmres<2>(b, c, s);
+    case 3: return launch_ngmres<3>(b, c, s);
+    case 4: return launch_ngmres<4>(b, c, s);
+    case 5: return launch_ngmres<5>(b, c, s);
+    case 6: return launch_ngmres<6>(b, c, s);
+    case 7: return launch_ngmres<7>(b, c, s);
+    case 8: return launch_ngmres<8>(b, c, s);
+    default: set_error("ngmres_depth %d outside 0..%d", c.ng_m, kNgMax); return DEHAZE_EINVAL;
+  }
 }
 
 int krylov_update(const KrylovBatch& b, hipStream_t s) {

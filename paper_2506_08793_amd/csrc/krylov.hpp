@@ -17,6 +17,14 @@
 //      (Jacobi preconditioner) in float32 until ||r_k|| <= inner_rtol ||r_n||
 //      or max_inner iterations.
 //   3. u_{n+1} = u_n + delta  (= L_{D(u_n)}^-1 Phi up to the inner tolerance).
+// With nonlinear GMRES acceleration (KConst::ng_m > 0, depth m), step 1 is
+// preceded by a least-squares mix: the current (trial) iterate ut with its
+// exact residual r(ut) is combined with the last m trial iterates U_j and
+// residuals R_j, u_mix = ut + sum_j b_j (ut - U_j) with b minimising
+// ||r(ut) + sum_j b_j (r(ut) - R_j)||; that combination of residuals is the
+// right-hand side of step 2, D stays frozen at ut, and step 3 applies the
+// correction to u_mix.  (ut, r(ut)) then joins the history.  A step whose
+// trial rho exceeds twice the lowest so far drops the history.
 // Every launch covers the tiles of all images; per-image scalars and flags
 // live on the device, so one outer step is a fixed launch sequence that can be
 // captured in a HIP graph and replayed.
@@ -37,6 +45,10 @@ constexpr int kUOW = 60;
 // multiples of it), so the sums, and every rounding that follows from them,
 // do not depend on the strip height.
 constexpr int kSBlk = 16;
+// Nonlinear GMRES: at most kNgMax earlier iterates; per tile, the Gram
+// entries (r - R_j).(r - R_l) for j <= l and (r - R_j).r.
+constexpr int kNgMax = 8;
+constexpr int kNPart = kNgMax * (kNgMax + 1) / 2 + kNgMax;
 
 struct KImg {
   int H, W, P;             // P: pitch of every plane, >= W + 1
@@ -58,6 +70,8 @@ struct KImg {
   float* s;
   float* t;
   float* x;                // 3 planes: the correction delta
+  double* Uh;              // nonlinear GMRES: m earlier trial iterates, 3 planes each (nullptr if m = 0)
+  float* Rh;               // their residuals, 3 planes each
 };
 
 struct KScal {
@@ -85,6 +99,13 @@ struct KScal {
   int it;                  // BiCGSTAB iteration of the current inner solve (1-based)
   int passes;              // residual passes that may start a step (defect-correction passes excluded)
   int exhausted;           // max_outer steps taken: done iterating
+  // nonlinear GMRES: mixing coefficients, lowest trial rho since the history
+  // was last dropped, entries in the history, slot of the next entry, and
+  // whether this step's mix is due
+  double ngb[kNgMax];
+  double ng_best;
+  int ng_nh, ng_slot, ng_pending;
+  int ng_drops;            // times the history was dropped
 };
 
 struct KConst {
@@ -103,11 +124,13 @@ struct KConst {
   int max_inner;
   int max_outer;
   int trial;               // launch-shape trials: the strip kernels skip the per-image state tests
+  int ng_m;                // nonlinear GMRES depth (0: plain lagged diffusivity)
 };
 KConst make_kconst(const dehaze_params& p);
 
-// Bytes of one image's planes (internal pitch) and its tile count.
-size_t krylov_image_bytes(int H, int W);
+// Bytes of one image's planes (internal pitch; ng_m earlier iterates for
+// nonlinear GMRES) and its tile count.
+size_t krylov_image_bytes(int H, int W, int ng_m);
 int krylov_tiles(int H, int W);
 int krylov_units(int H, int W, int us);
 int krylov_blocks(int H, int W);
@@ -120,7 +143,7 @@ void krylov_strip_rows(int n, const int* H, const int* W, int* us);
 // Fills a descriptor whose planes live at `base` (krylov_image_bytes bytes,
 // 256-byte aligned); phi/lam are carved here too and returned through the
 // descriptor (the front end writes them).
-KImg krylov_carve(void* base, int H, int W, int tile0, int unit0, int blk0, int us);
+KImg krylov_carve(void* base, int H, int W, int tile0, int unit0, int blk0, int us, int ng_m);
 
 struct KrylovBatch {
   const KImg* d_imgs;      // device copy of the descriptors
@@ -132,6 +155,7 @@ struct KrylovBatch {
   const int* d_unit_img;   // image index of every strip wavefront
   double* d_upart;         // kKPart doubles per strip wavefront
   int nunits;
+  double* d_npart;         // nonlinear GMRES: kNPart doubles per tile (nullptr if unused)
 };
 
 // Uploads the descriptors and the strip-wavefront -> image map (b.nunits
@@ -155,6 +179,10 @@ int krylov_time_strips(const KrylovBatch& b, const KConst& c, int reps, hipStrea
 // keeps its own iteration count; an inner solve ends at its tolerance or after
 // max_inner iterations).
 int krylov_inner(const KrylovBatch& b, const KConst& c, hipStream_t s);
+// Nonlinear GMRES mix for every image whose residual pass just ended a step
+// (Gram sums, least squares, mix and history update); it then starts the
+// image's inner solve.  Nothing to do when c.ng_m = 0.
+int krylov_ngmres(const KrylovBatch& b, const KConst& c, hipStream_t s);
 // u += delta.
 int krylov_update(const KrylovBatch& b, hipStream_t s);
 // u (float64) -> out (float, dense pitch W), or unchanged into a double array.

@@ -238,18 +238,21 @@ struct KrylovPlan {
   double* d_part = nullptr;
   int* d_unit_img = nullptr;
   double* d_upart = nullptr;
+  double* d_npart = nullptr;
   float* u0w = nullptr;   // warm start B (+ the network's correction), planar pitch W
   char* cnn_ws = nullptr;
   size_t bytes = 0;
 };
 
-KrylovPlan plan_krylov(void* ws, int H, int W, bool warm) {
+KrylovPlan plan_krylov(void* ws, int H, int W, const dehaze_params& p) {
+  const bool warm = p.warm_start != 0;
+  const int ng = p.ngmres_depth;
   KrylovPlan pl;
   Carver cv(ws, ~size_t(0));
-  char* arena = cv.take<char>(krylov_image_bytes(H, W));
+  char* arena = cv.take<char>(krylov_image_bytes(H, W, ng));
   int us = 32;
   krylov_strip_rows(1, &H, &W, &us);
-  pl.img = krylov_carve(arena, H, W, 0, 0, 0, us);
+  pl.img = krylov_carve(arena, H, W, 0, 0, 0, us, ng);
   const int nt = krylov_tiles(H, W);
   // room for the most strip wavefronts (kSBlk rows each), one partial-sum
   // slot per block
@@ -261,6 +264,7 @@ KrylovPlan plan_krylov(void* ws, int H, int W, bool warm) {
   pl.d_part = cv.take<double>(static_cast<size_t>(kKPart) * nt);
   pl.d_unit_img = cv.take<int>(nu);
   pl.d_upart = cv.take<double>(static_cast<size_t>(kKPart) * nu);
+  if (ng > 0) pl.d_npart = cv.take<double>(static_cast<size_t>(kNPart) * nt);
   if (warm) {
     pl.u0w = cv.take<float>(3 * static_cast<size_t>(H) * W);
     pl.cnn_ws = cv.take<char>(cnn_forward_bytes(1, H, W));
@@ -312,6 +316,7 @@ int outer_step(const KrylovBatch& b, const KConst& kc, const dehaze_params& p, h
 int tick_step(const KrylovBatch& b, const KConst& kc, hipStream_t s) {
   int rc;
   if ((rc = krylov_residual(b, kc, 0, s))) return rc;
+  if ((rc = krylov_ngmres(b, kc, s))) return rc;
   if ((rc = krylov_inner(b, kc, s))) return rc;
   return krylov_update(b, s);
 }
@@ -336,7 +341,7 @@ namespace {
 bool same_key(const GraphCache& g, const KrylovBatch& b, const KConst& kc, int steps, const dehaze_params& p) {
   return g.exec && g.b.d_imgs == b.d_imgs && g.b.d_scal == b.d_scal && g.b.d_tile_img == b.d_tile_img &&
          g.b.d_part == b.d_part && g.b.nimg == b.nimg && g.b.ntiles == b.ntiles &&
-         g.b.d_unit_img == b.d_unit_img && g.b.d_upart == b.d_upart && g.b.nunits == b.nunits && g.steps == steps &&
+         g.b.d_unit_img == b.d_unit_img && g.b.d_upart == b.d_upart && g.b.nunits == b.nunits && g.b.d_npart == b.d_npart && g.steps == steps &&
          g.max_inner == p.max_inner && g.refine == p.inner_refine && std::memcmp(&g.kc, &kc, sizeof(kc)) == 0;
 }
 
@@ -553,14 +558,14 @@ int image_status(const KScal& k, const dehaze_params& p) {
 
 int run_krylov(Ctx& ctx, const SolveArgs& a, const dehaze_params& p, dehaze_stats* st, hipStream_t s) {
   const int H = a.H, W = a.W;
-  KrylovPlan pl = plan_krylov(a.ws, H, W, p.warm_start != 0);
+  KrylovPlan pl = plan_krylov(a.ws, H, W, p);
   const int P = pl.img.P;
   int rc;
   if ((rc = launch_to_planar(a.I, a.dtype, a.layout, H, W, a.pitch, pl.Ip, P, s))) return rc;
   FusedOut fo{nullptr, nullptr, const_cast<float*>(pl.img.lam), const_cast<float*>(pl.img.phi), P, P};
   if ((rc = launch_prior_fused(nullptr, pl.Ip, P, a.t, W, a.A, H, W, p, fo, s))) return rc;
   KrylovBatch b{pl.d_imgs, pl.d_scal, pl.d_tile_img, pl.d_part, 1, pl.img.ntiles,
-                pl.d_unit_img, pl.d_upart, pl.img.nunits};
+                pl.d_unit_img, pl.d_upart, pl.img.nunits, pl.d_npart};
   const float* u0 = a.u0;
   if (p.warm_start) {
     const size_t plane = static_cast<size_t>(H) * P;
@@ -608,6 +613,7 @@ struct BatchPlan {
   double* d_part = nullptr;
   int* d_unit_img = nullptr;
   double* d_upart = nullptr;
+  double* d_npart = nullptr;
   std::vector<float*> u0w;  // warm starts B (+ the network's correction)
   char* cnn_ws = nullptr;
   int ntiles = 0;
@@ -635,8 +641,8 @@ BatchPlan plan_batch(void* ws, int n, const dehaze_image* im, const dehaze_param
   krylov_strip_rows(n, hs.data(), wsz.data(), us.data());
   int tile0 = 0, unit0 = 0, blk0 = 0;
   for (int i = 0; i < n; ++i) {
-    char* arena = cv.take<char>(krylov_image_bytes(im[i].H, im[i].W));
-    pl.imgs.push_back(krylov_carve(arena, im[i].H, im[i].W, tile0, unit0, blk0, us[i]));
+    char* arena = cv.take<char>(krylov_image_bytes(im[i].H, im[i].W, p.ngmres_depth));
+    pl.imgs.push_back(krylov_carve(arena, im[i].H, im[i].W, tile0, unit0, blk0, us[i], p.ngmres_depth));
     tile0 += pl.imgs.back().ntiles;
     unit0 += pl.imgs.back().nunits;
     blk0 += pl.imgs.back().nblk;
@@ -656,6 +662,7 @@ BatchPlan plan_batch(void* ws, int n, const dehaze_image* im, const dehaze_param
   // slot per block
   pl.d_unit_img = cv.take<int>(blk0);
   pl.d_upart = cv.take<double>(static_cast<size_t>(kKPart) * blk0);
+  if (p.ngmres_depth > 0) pl.d_npart = cv.take<double>(static_cast<size_t>(kNPart) * tile0);
   pl.bytes = cv.used();
   return pl;
 }
@@ -706,7 +713,7 @@ int batch_front_end(Ctx& ctx, const BatchPlan& pl, int i, const dehaze_image& m,
 }  // namespace
 
 size_t solver_workspace_bytes(int H, int W, const dehaze_params& p) {
-  if (p.scheme == DEHAZE_PICARD_KRYLOV) return plan_krylov(nullptr, H, W, p.warm_start != 0).bytes;
+  if (p.scheme == DEHAZE_PICARD_KRYLOV) return plan_krylov(nullptr, H, W, p).bytes;
   return plan_sweeps(nullptr, H, W).bytes;
 }
 
@@ -782,7 +789,8 @@ int solve_batch(Ctx& ctx, int n, const dehaze_image* im, int dtype, int layout, 
     if ((rc = batch_front_end(ctx, pl, i, im[i], dtype, layout, p, &A_used[i], s))) return rc;
     u0[i] = p.warm_start ? pl.u0w[i] : im[i].u0;
   }
-  KrylovBatch b{pl.d_imgs, pl.d_scal, pl.d_tile_img, pl.d_part, n, pl.ntiles, pl.d_unit_img, pl.d_upart, pl.nunits};
+  KrylovBatch b{pl.d_imgs, pl.d_scal, pl.d_tile_img, pl.d_part, n, pl.ntiles, pl.d_unit_img, pl.d_upart, pl.nunits,
+                pl.d_npart};
   if ((rc = krylov_init(b, pl.imgs.data(), u0.data(), s))) return rc;
   if ((rc = choose_strips(ctx, pl.imgs, b, p, s))) return rc;
   std::vector<KScal> hs(n);
